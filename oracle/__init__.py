@@ -1,0 +1,139 @@
+"""CPU oracle for per-pixel tile masks -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  It shares no code with the GPU path and the product never
+calls it.  The arithmetic lives in ``hv_oracle.c`` (plain C, FP64, no FMA
+contraction); this module only marshals numpy arrays through ctypes.
+
+What it computes is the plain definition of the binary mask read from the
+paper's Algorithm 1 (Sec. 3.2.1): pixel (i, j) of tile (z, x, y) is lit iff
+the distance D from its centre to the nearest object is <= r px.  Each pixel
+also gets a tri-state value (0 unlit, 1 lit, 2 ambiguous when |D - r| <=
+1e-6 px) and per-tile work counters.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+POINTS, SEGMENTS, POLYGON_EDGES = 0, 1, 2
+MERC01 = 0x100
+BAND = 1e-6
+UNLIT, LIT, AMBIGUOUS = 0, 1, 2
+# per-tile counters
+C_NODES, C_LIT, C_AMB, C_NBOX_UNLIT, C_UNLIT_CAND = range(5)
+
+_lib = None
+
+
+def _load(path: str | None = None):
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = _bind(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _bind(lib):
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    lib.oracle_build.restype = P
+    lib.oracle_build.argtypes = [P, ctypes.c_int, I64]
+    lib.oracle_free.restype = None
+    lib.oracle_free.argtypes = [P]
+    lib.oracle_render.restype = ctypes.c_int
+    lib.oracle_render.argtypes = [P, P, I64, P, P, P, P, P, ctypes.c_int]
+    lib.oracle_project.restype = ctypes.c_int
+    lib.oracle_project.argtypes = [P, I64, P, P]
+    lib.oracle_node_count.restype = I64
+    lib.oracle_node_count.argtypes = [P]
+    lib.oracle_depth.restype = ctypes.c_int
+    lib.oracle_depth.argtypes = [P]
+    lib.oracle_root_box.restype = ctypes.c_int
+    lib.oracle_root_box.argtypes = [P, P]
+    return lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def project(lonlat: np.ndarray, lib_path: str | None = None):
+    """(n,2) lon/lat degrees -> (X, Y) normalised Web-Mercator, y south."""
+    lib = _load(lib_path)
+    ll = np.ascontiguousarray(lonlat, dtype=np.float64).reshape(-1, 2)
+    X = np.empty(ll.shape[0])
+    Y = np.empty(ll.shape[0])
+    lib.oracle_project(_ptr(ll), ll.shape[0], _ptr(X), _ptr(Y))
+    return X, Y
+
+
+def default_threads() -> int:
+    return len(os.sched_getaffinity(0))
+
+
+class OracleIndex:
+    """Serial STR R-tree over points / segments / polygon edges."""
+
+    def __init__(self, objects: np.ndarray, kind: int, merc01: bool = False,
+                 lib_path: str | None = None):
+        self._lib = _load(lib_path)
+        width = 2 if kind == POINTS else 4
+        self._obj = np.ascontiguousarray(objects, dtype=np.float64).reshape(-1, width)
+        self.kind = kind
+        self.n = self._obj.shape[0]
+        self._h = self._lib.oracle_build(_ptr(self._obj), kind | (MERC01 if merc01 else 0), self.n)
+        if not self._h:
+            raise MemoryError("oracle_build failed")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.oracle_free(h)
+            self._h = None
+
+    @property
+    def node_count(self) -> int:
+        return int(self._lib.oracle_node_count(self._h))
+
+    @property
+    def depth(self) -> int:
+        return int(self._lib.oracle_depth(self._h))
+
+    def root_box(self):
+        out = np.empty(4)
+        return out if self._lib.oracle_root_box(self._h, _ptr(out)) else None
+
+    def render(self, tiles: np.ndarray, r, nthreads: int | None = None,
+               want_bit: bool = True, want_dist: bool = False, want_counters: bool = False):
+        """Returns dict with 'tri' (n,256,256) u8 and optionally 'bit', 'dist',
+        'counters' (n,5) int64.  ``r`` is a scalar or one value per tile."""
+        t = np.ascontiguousarray(tiles, dtype=np.int32).reshape(-1, 3)
+        n = t.shape[0]
+        rr = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=np.float64), (n,)))
+        tri = np.empty((n, 256, 256), dtype=np.uint8)
+        bit = np.empty((n, 256, 256), dtype=np.uint8) if want_bit else None
+        dist = np.empty((n, 256, 256), dtype=np.float64) if want_dist else None
+        cnt = np.zeros((n, 5), dtype=np.int64) if want_counters else None
+        th = default_threads() if nthreads is None else nthreads
+        rc = self._lib.oracle_render(self._h, _ptr(t), n, _ptr(rr), _ptr(tri), _ptr(bit),
+                                     _ptr(dist), _ptr(cnt), th)
+        if rc != 0:
+            raise ValueError("oracle_render rejected its arguments")
+        out = {"tri": tri}
+        if want_bit:
+            out["bit"] = bit
+        if want_dist:
+            out["dist"] = dist
+        if want_counters:
+            out["counters"] = cnt
+        return out

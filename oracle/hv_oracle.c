@@ -1,0 +1,447 @@
+/*
+ * hv_oracle.c -- CPU oracle for per-pixel tile masks.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code with
+ * the GPU path (no headers, no helpers, no constants) and nothing in the
+ * product calls it.
+ *
+ * What it computes (HiVision, arXiv 2005.12489, Sec. 3.2.1 and Algorithm 1,
+ * read in binary form):
+ *   For tile (z,x,y) and pixel (i,j) (i = column, j = row from the north
+ *   edge), with the style's radius or half-width r in pixels, the pixel's
+ *   centre c is tested against every indexed object.  D(c) is the Euclidean
+ *   distance from c to the nearest object, measured in world pixels of zoom z
+ *   (one pixel is the resolution R_z of Algorithm 1, and the radius is
+ *   R = N * R_z).  The pixel is lit iff D(c) <= r (the comparisons of
+ *   Algorithm 1 are inclusive).
+ *
+ *   The paper's Algorithm 1 finds objects through R-tree box queries whose
+ *   boxes are squares around the pixel (OuterBox) and only then measures
+ *   distances ("filter, then refine").  This oracle does the same with one
+ *   query box per pixel, the square c +- (r + 1e-5) px, followed by the exact
+ *   distance to every object returned.  Like Algorithm 1's InnerBox step with
+ *   limit(1), the search stops early once an object certainly lies within r.
+ *
+ * Readings of the paper made here (it is silent on each):
+ *   - Space: Web-Mercator normalised to [0,1]^2, y = 0 at the north edge
+ *     (WMTS/XYZ tile rows count from the top).  World size at zoom z is
+ *     S = 256 * 2^z pixels, so R_z = 1/S.  Latitude is clamped to
+ *     +-85.0511287798066 deg; there is no antimeridian wrap.
+ *   - The pixel's own value is that of its centre sample.
+ *   - Distance to a segment is the distance to the closed segment; a
+ *     zero-length segment is a point.  Polygons arrive already split into
+ *     edges (Sec. 3.1), each treated as a segment.
+ *   - Tri-state output: pixels whose D lies within 1e-6 px of r are reported
+ *     as ambiguous; elsewhere the result is certain at FP64 precision.
+ *
+ * Index: a serial Sort-Tile-Recursive packed R-tree (Leutenegger, Lopez and
+ * Edgington, 1997) with fanout 16 and exact FP64 bounding boxes, built over
+ * the objects (points, or segments split from linestrings and polygon edges,
+ * as in the paper's RtreeP / RtreeL / RtreeE of Sec. 3.1).
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -pthread -lm
+ * (no -ffast-math; no FMA contraction, so every product is rounded once).
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_POINTS 0
+#define OR_SEGMENTS 1
+#define OR_EDGES 2
+#define OR_MERC01 0x100
+
+#define OR_FANOUT 16
+#define OR_BAND 1e-6          /* ambiguity half-width, px */
+#define OR_QUERY_PAD 1e-5     /* query box margin beyond r, px */
+#define OR_MAX_LAT 85.0511287798066
+
+static const double OR_PI = 3.14159265358979323846;
+
+typedef struct { double x0, y0, x1, y1; } obox;
+
+typedef struct {
+    int kind;
+    int64_t n;
+    double *ax, *ay, *bx, *by;   /* normalised Mercator; points have b == a */
+    int64_t n_nodes;
+    obox *box;                   /* node bounding boxes */
+    int64_t *first;              /* index into child[] */
+    int32_t *count;
+    uint8_t *leaf;               /* 1: children are object ids */
+    int64_t *child;
+    int64_t root;                /* -1 for an empty index */
+    int depth;
+} or_index;
+
+/* ----------------------------------------------------------- projection */
+/* lon/lat in degrees -> normalised Web-Mercator X (east), Y (south). */
+static void project_one(double lon, double lat, double *X, double *Y)
+{
+    if (lat > OR_MAX_LAT) lat = OR_MAX_LAT;
+    if (lat < -OR_MAX_LAT) lat = -OR_MAX_LAT;
+    double phi = lat * (OR_PI / 180.0);
+    *X = (lon + 180.0) / 360.0;
+    *Y = 0.5 - log(tan(OR_PI / 4.0 + phi / 2.0)) / (2.0 * OR_PI);
+}
+
+int oracle_project(const double *lonlat, int64_t n, double *X, double *Y)
+{
+    for (int64_t k = 0; k < n; ++k) project_one(lonlat[2 * k], lonlat[2 * k + 1], &X[k], &Y[k]);
+    return 0;
+}
+
+/* ------------------------------------------------------------ STR build */
+typedef struct { obox b; double cx, cy; int64_t id; } entry;
+
+static int cmp_cx(const void *a, const void *b)
+{
+    double u = ((const entry *)a)->cx, v = ((const entry *)b)->cx;
+    return (u > v) - (u < v);
+}
+
+static int cmp_cy(const void *a, const void *b)
+{
+    double u = ((const entry *)a)->cy, v = ((const entry *)b)->cy;
+    return (u > v) - (u < v);
+}
+
+static obox obj_box(const or_index *ix, int64_t k)
+{
+    obox b;
+    b.x0 = fmin(ix->ax[k], ix->bx[k]);
+    b.x1 = fmax(ix->ax[k], ix->bx[k]);
+    b.y0 = fmin(ix->ay[k], ix->by[k]);
+    b.y1 = fmax(ix->ay[k], ix->by[k]);
+    return b;
+}
+
+/* Packs `ne` entries into ceil(ne/F) nodes with STR; appends the nodes. */
+static int str_level(or_index *ix, entry *e, int64_t ne, int is_leaf,
+                     int64_t *node_cap, int64_t *child_cap, int64_t *n_child)
+{
+    int64_t P = (ne + OR_FANOUT - 1) / OR_FANOUT;
+    int64_t Sl = (int64_t)ceil(sqrt((double)P));
+    int64_t slice = Sl * OR_FANOUT;
+    qsort(e, (size_t)ne, sizeof(entry), cmp_cx);
+    for (int64_t s = 0; s < ne; s += slice) {
+        int64_t m = ne - s < slice ? ne - s : slice;
+        qsort(e + s, (size_t)m, sizeof(entry), cmp_cy);
+    }
+    for (int64_t s = 0; s < ne; s += OR_FANOUT) {
+        int64_t m = ne - s < OR_FANOUT ? ne - s : OR_FANOUT;
+        if (ix->n_nodes == *node_cap) {
+            *node_cap *= 2;
+            ix->box = realloc(ix->box, (size_t)*node_cap * sizeof(obox));
+            ix->first = realloc(ix->first, (size_t)*node_cap * sizeof(int64_t));
+            ix->count = realloc(ix->count, (size_t)*node_cap * sizeof(int32_t));
+            ix->leaf = realloc(ix->leaf, (size_t)*node_cap);
+            if (!ix->box || !ix->first || !ix->count || !ix->leaf) return -1;
+        }
+        while (*n_child + m > *child_cap) {
+            *child_cap *= 2;
+            ix->child = realloc(ix->child, (size_t)*child_cap * sizeof(int64_t));
+            if (!ix->child) return -1;
+        }
+        int64_t nd = ix->n_nodes++;
+        obox b = e[s].b;
+        for (int64_t k = 0; k < m; ++k) {
+            const obox *c = &e[s + k].b;
+            if (c->x0 < b.x0) b.x0 = c->x0;
+            if (c->y0 < b.y0) b.y0 = c->y0;
+            if (c->x1 > b.x1) b.x1 = c->x1;
+            if (c->y1 > b.y1) b.y1 = c->y1;
+            ix->child[*n_child + k] = e[s + k].id;
+        }
+        ix->box[nd] = b;
+        ix->first[nd] = *n_child;
+        ix->count[nd] = (int32_t)m;
+        ix->leaf[nd] = (uint8_t)is_leaf;
+        *n_child += m;
+    }
+    return 0;
+}
+
+void oracle_free(void *h)
+{
+    or_index *ix = (or_index *)h;
+    if (!ix) return;
+    free(ix->ax); free(ix->ay); free(ix->bx); free(ix->by);
+    free(ix->box); free(ix->first); free(ix->count); free(ix->leaf); free(ix->child);
+    free(ix);
+}
+
+/* objects: points (n,2) lon,lat  or  segments/edges (n,4) lon0,lat0,lon1,lat1;
+ * with OR_MERC01 in kind the values are already normalised X,Y. */
+void *oracle_build(const double *objects, int kind, int64_t n)
+{
+    int merc = (kind & OR_MERC01) != 0;
+    int k = kind & 0xff;
+    if (n < 0 || (k != OR_POINTS && k != OR_SEGMENTS && k != OR_EDGES)) return NULL;
+    or_index *ix = calloc(1, sizeof(or_index));
+    if (!ix) return NULL;
+    ix->kind = k;
+    ix->n = n;
+    ix->root = -1;
+    size_t sz = (size_t)(n > 0 ? n : 1) * sizeof(double);
+    ix->ax = malloc(sz); ix->ay = malloc(sz); ix->bx = malloc(sz); ix->by = malloc(sz);
+    if (!ix->ax || !ix->ay || !ix->bx || !ix->by) { oracle_free(ix); return NULL; }
+    int w = (k == OR_POINTS) ? 2 : 4;
+    for (int64_t q = 0; q < n; ++q) {
+        const double *o = objects + (size_t)w * q;
+        if (merc) {
+            ix->ax[q] = o[0]; ix->ay[q] = o[1];
+            ix->bx[q] = (w == 4) ? o[2] : o[0];
+            ix->by[q] = (w == 4) ? o[3] : o[1];
+        } else {
+            project_one(o[0], o[1], &ix->ax[q], &ix->ay[q]);
+            if (w == 4) project_one(o[2], o[3], &ix->bx[q], &ix->by[q]);
+            else { ix->bx[q] = ix->ax[q]; ix->by[q] = ix->ay[q]; }
+        }
+    }
+    if (n == 0) return ix;
+
+    int64_t node_cap = n / 8 + 16, child_cap = n + n / 8 + 16, n_child = 0;
+    ix->box = malloc((size_t)node_cap * sizeof(obox));
+    ix->first = malloc((size_t)node_cap * sizeof(int64_t));
+    ix->count = malloc((size_t)node_cap * sizeof(int32_t));
+    ix->leaf = malloc((size_t)node_cap);
+    ix->child = malloc((size_t)child_cap * sizeof(int64_t));
+    entry *e = malloc((size_t)n * sizeof(entry));
+    if (!ix->box || !ix->first || !ix->count || !ix->leaf || !ix->child || !e) {
+        free(e); oracle_free(ix); return NULL;
+    }
+    for (int64_t q = 0; q < n; ++q) {
+        e[q].b = obj_box(ix, q);
+        e[q].cx = 0.5 * (e[q].b.x0 + e[q].b.x1);
+        e[q].cy = 0.5 * (e[q].b.y0 + e[q].b.y1);
+        e[q].id = q;
+    }
+    int64_t ne = n, lvl_first = 0;
+    int is_leaf = 1;
+    ix->depth = 0;
+    for (;;) {
+        lvl_first = ix->n_nodes;
+        if (str_level(ix, e, ne, is_leaf, &node_cap, &child_cap, &n_child)) {
+            free(e); oracle_free(ix); return NULL;
+        }
+        ix->depth++;
+        int64_t made = ix->n_nodes - lvl_first;
+        if (made == 1) break;
+        for (int64_t q = 0; q < made; ++q) {
+            int64_t nd = lvl_first + q;
+            e[q].b = ix->box[nd];
+            e[q].cx = 0.5 * (e[q].b.x0 + e[q].b.x1);
+            e[q].cy = 0.5 * (e[q].b.y0 + e[q].b.y1);
+            e[q].id = nd;
+        }
+        ne = made;
+        is_leaf = 0;
+    }
+    ix->root = ix->n_nodes - 1;
+    free(e);
+    return ix;
+}
+
+int64_t oracle_node_count(const void *h) { return ((const or_index *)h)->n_nodes; }
+int oracle_depth(const void *h) { return ((const or_index *)h)->depth; }
+
+/* Root bounding box (normalised); returns 0 for an empty index. */
+int oracle_root_box(const void *h, double *out4)
+{
+    const or_index *ix = (const or_index *)h;
+    if (ix->root < 0) return 0;
+    out4[0] = ix->box[ix->root].x0; out4[1] = ix->box[ix->root].y0;
+    out4[2] = ix->box[ix->root].x1; out4[3] = ix->box[ix->root].y1;
+    return 1;
+}
+
+/* ------------------------------------------------------------ predicates */
+static int box_meets(const obox *a, const obox *b)
+{
+    return a->x0 <= b->x1 && b->x0 <= a->x1 && a->y0 <= b->y1 && b->y0 <= a->y1;
+}
+
+/* Distance (px) from the pixel centre (px,py) to object k, all in the
+ * tile-local pixel frame: u = X*S - 256*x, v = Y*S - 256*y. */
+static double obj_dist(const or_index *ix, int64_t k, double S, double ox, double oy,
+                       double px, double py)
+{
+    double ax = ix->ax[k] * S - ox, ay = ix->ay[k] * S - oy;
+    if (ix->kind == OR_POINTS) {
+        double ex = px - ax, ey = py - ay;
+        return sqrt(ex * ex + ey * ey);
+    }
+    double bx = ix->bx[k] * S - ox, by = ix->by[k] * S - oy;
+    double dx = bx - ax, dy = by - ay;
+    double len2 = dx * dx + dy * dy;
+    double t = 0.0;
+    if (len2 > 0.0) {
+        t = ((px - ax) * dx + (py - ay) * dy) / len2;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+    }
+    double ex = px - (ax + t * dx), ey = py - (ay + t * dy);
+    return sqrt(ex * ex + ey * ey);
+}
+
+/* ------------------------------------------------------------ rendering */
+enum { C_NODES = 0, C_LIT = 1, C_AMB = 2, C_NBOX_UNLIT = 3, C_UNLIT_CAND = 4, C_NCOUNT = 5 };
+
+typedef struct {
+    int64_t *stack; int64_t stack_cap;
+    int64_t *pix_ids; int64_t pix_cap;       /* ids meeting c +- r for one pixel */
+    int64_t *tile_ids; int64_t tile_cap, tile_n;
+} scratch;
+
+static int grow(int64_t **a, int64_t *cap, int64_t need)
+{
+    if (need <= *cap) return 0;
+    int64_t c = *cap ? *cap : 256;
+    while (c < need) c *= 2;
+    int64_t *p = realloc(*a, (size_t)c * sizeof(int64_t));
+    if (!p) return -1;
+    *a = p; *cap = c;
+    return 0;
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t u = *(const int64_t *)a, v = *(const int64_t *)b;
+    return (u > v) - (u < v);
+}
+
+static int render_tile(const or_index *ix, int z, int64_t tx, int64_t ty, double r,
+                       uint8_t *tri, uint8_t *bit, double *dist, int64_t *cnt, scratch *sc)
+{
+    const double S = 256.0 * ldexp(1.0, z);
+    const double ox = 256.0 * (double)tx, oy = 256.0 * (double)ty;
+    const double h = r + OR_QUERY_PAD;
+    int64_t nodes = 0, lit = 0, amb = 0, nbox_unlit = 0;
+    sc->tile_n = 0;
+    if (grow(&sc->stack, &sc->stack_cap, (int64_t)OR_FANOUT * (ix->depth + 2))) return -1;
+    for (int j = 0; j < 256; ++j) {
+        for (int i = 0; i < 256; ++i) {
+            const double px = i + 0.5, py = j + 0.5;         /* tile-local centre */
+            const double cx = ox + px, cy = oy + py;          /* world pixels */
+            obox q = { (cx - h) / S, (cy - h) / S, (cx + h) / S, (cy + h) / S };
+            obox qr = { (cx - r) / S, (cy - r) / S, (cx + r) / S, (cy + r) / S };
+            double D = INFINITY;
+            int64_t npix = 0;
+            int certain = 0;
+            int64_t sp = 0;
+            if (ix->root >= 0) sc->stack[sp++] = ix->root;
+            while (sp > 0 && !certain) {
+                int64_t nd = sc->stack[--sp];
+                ++nodes;
+                if (!box_meets(&ix->box[nd], &q)) continue;
+                const int64_t *ch = ix->child + ix->first[nd];
+                if (!ix->leaf[nd]) {
+                    for (int32_t c = 0; c < ix->count[nd]; ++c) sc->stack[sp++] = ch[c];
+                    continue;
+                }
+                for (int32_t c = 0; c < ix->count[nd]; ++c) {
+                    int64_t k = ch[c];
+                    obox b = obj_box(ix, k);
+                    if (!box_meets(&b, &q)) continue;
+                    if (box_meets(&b, &qr)) {
+                        if (grow(&sc->pix_ids, &sc->pix_cap, npix + 1)) return -1;
+                        sc->pix_ids[npix++] = k;
+                    }
+                    double d = obj_dist(ix, k, S, ox, oy, px, py);
+                    if (d < D) D = d;
+                    if (D < r - OR_BAND) { certain = 1; break; }
+                }
+            }
+            int b = D <= r;
+            uint8_t t = D < r - OR_BAND ? 1 : (D > r + OR_BAND ? 0 : 2);
+            size_t p = (size_t)j * 256 + (size_t)i;
+            tri[p] = t;
+            if (bit) bit[p] = (uint8_t)b;
+            if (dist) dist[p] = D;
+            lit += b;
+            amb += (t == 2);
+            if (!b) {
+                nbox_unlit += npix;
+                if (grow(&sc->tile_ids, &sc->tile_cap, sc->tile_n + npix)) return -1;
+                memcpy(sc->tile_ids + sc->tile_n, sc->pix_ids, (size_t)npix * sizeof(int64_t));
+                sc->tile_n += npix;
+            }
+        }
+    }
+    int64_t uniq = 0;
+    if (sc->tile_n > 0) {
+        qsort(sc->tile_ids, (size_t)sc->tile_n, sizeof(int64_t), cmp_i64);
+        uniq = 1;
+        for (int64_t q = 1; q < sc->tile_n; ++q) uniq += sc->tile_ids[q] != sc->tile_ids[q - 1];
+    }
+    if (cnt) {
+        cnt[C_NODES] = nodes; cnt[C_LIT] = lit; cnt[C_AMB] = amb;
+        cnt[C_NBOX_UNLIT] = nbox_unlit; cnt[C_UNLIT_CAND] = uniq;
+    }
+    return 0;
+}
+
+typedef struct {
+    const or_index *ix;
+    const int32_t *tiles;
+    const double *r;
+    int64_t ntiles;
+    uint8_t *tri, *bit;
+    double *dist;
+    int64_t *cnt;
+    int64_t next;          /* shared tile counter */
+    int err;
+} job;
+
+static void *worker(void *arg)
+{
+    job *jb = (job *)arg;
+    scratch sc;
+    memset(&sc, 0, sizeof sc);
+    for (;;) {
+        int64_t t = __atomic_fetch_add(&jb->next, 1, __ATOMIC_RELAXED);
+        if (t >= jb->ntiles) break;
+        const int32_t *tl = jb->tiles + 3 * t;
+        size_t off = (size_t)t * 65536;
+        if (render_tile(jb->ix, tl[0], tl[1], tl[2], jb->r[t], jb->tri + off,
+                        jb->bit ? jb->bit + off : NULL, jb->dist ? jb->dist + off : NULL,
+                        jb->cnt ? jb->cnt + C_NCOUNT * t : NULL, &sc))
+            __atomic_store_n(&jb->err, 1, __ATOMIC_RELAXED);
+    }
+    free(sc.stack); free(sc.pix_ids); free(sc.tile_ids);
+    return NULL;
+}
+
+/* tiles: (ntiles,3) int32 z,x,y (0 <= z <= 30, 0 <= x,y < 2^z); r: per-tile
+ * radius or half-width in px.  Outputs per tile, 256x256 row-major from the
+ * north-west pixel: tri (0 unlit, 1 lit, 2 ambiguous), optional bit = [D<=r],
+ * optional dist = D (an upper bound where the search stopped early on a
+ * certain hit), optional counters (5 per tile).  Returns 0, or -1 on a bad
+ * argument or allocation failure. */
+int oracle_render(const void *h, const int32_t *tiles, int64_t ntiles, const double *r,
+                  uint8_t *tri, uint8_t *bit, double *dist, int64_t *counters, int nthreads)
+{
+    const or_index *ix = (const or_index *)h;
+    if (!ix || ntiles < 0 || (ntiles > 0 && (!tiles || !r || !tri))) return -1;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int32_t z = tiles[3 * t], x = tiles[3 * t + 1], y = tiles[3 * t + 2];
+        if (z < 0 || z > 30 || x < 0 || y < 0 || (int64_t)x >= ((int64_t)1 << z) ||
+            (int64_t)y >= ((int64_t)1 << z) || !(r[t] > 0.0) || !isfinite(r[t]))
+            return -1;
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    job jb = { ix, tiles, r, ntiles, tri, bit, dist, counters, 0, 0 };
+    pthread_t th[256];
+    int started = 0;
+    for (int k = 1; k < nthreads; ++k)
+        if (pthread_create(&th[started], NULL, worker, &jb) == 0) ++started;
+    worker(&jb);
+    for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
+    return jb.err ? -1 : 0;
+}

@@ -1,0 +1,26 @@
+"""Runs the oracle pins against one oracle library; exit 0 iff all pass.
+
+Used by the mutation test: each planted mistake must make some pin fail.
+"""
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import oracle_pins  # noqa: E402
+
+lib = sys.argv[1]
+for name, fn in oracle_pins.PINS.items():
+    try:
+        fn(lib_path=lib)
+    except AssertionError as e:
+        print(f"caught by {name}: {e!r}"[:300])
+        sys.exit(1)
+try:
+    oracle_pins.pin_ckdtree(lib_path=lib, n_tiles=16)
+except AssertionError as e:
+    print(f"caught by ckdtree: {e!r}"[:300])
+    sys.exit(1)
+print("not caught")
+sys.exit(0)

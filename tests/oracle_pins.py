@@ -1,0 +1,333 @@
+"""Pins for the CPU oracle: each checks it against something other than itself.
+
+Every pin takes ``lib_path`` (None = the built oracle) so that the mutation
+test can run the same pins against copies of the oracle with planted
+mistakes.  A pin raises AssertionError when the oracle disagrees.
+
+Kinds of pins used (paper sections in brackets):
+  closed forms   -- projection constants, lattice-disk counts, segment
+                    special cases [Sec. 3.2.1, Algorithm 1]
+  brute force    -- every object against every pixel, numpy [definition]
+  library        -- scipy cKDTree nearest-neighbour distance [points]
+  invariants     -- union, permutation, monotone in r, own pixel,
+                    parent-empty => child-empty, tile translation
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+import oracle
+from brute import brute_distance, near_band_edge, objects_merc01, tri_state
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _ix(objs, kind, merc01=True, lib_path=None):
+    return oracle.OracleIndex(np.asarray(objs, dtype=np.float64), kind, merc01=merc01,
+                              lib_path=lib_path)
+
+
+def _px_to_merc(z, x, y, u, v):
+    """Tile-local pixel coordinates -> normalised Mercator (exact for dyadic u, v)."""
+    S = 256.0 * 2.0 ** z
+    return ((256.0 * x + np.asarray(u, dtype=np.float64)) / S,
+            (256.0 * y + np.asarray(v, dtype=np.float64)) / S)
+
+
+def _seg(z, x, y, u0, v0, u1, v1):
+    a = _px_to_merc(z, x, y, u0, v0)
+    b = _px_to_merc(z, x, y, u1, v1)
+    return np.array([[a[0], a[1], b[0], b[1]]])
+
+
+def _counts(out, t=0):
+    tri = out["tri"][t]
+    return int(out["bit"][t].sum()), int((tri == 1).sum()), int((tri == 2).sum())
+
+
+# ------------------------------------------------------------ projection
+def pin_projection(lib_path=None):
+    # X is exact for dyadic longitudes -180 + 360 k / 2^m.
+    lons, want = [], []
+    for m in range(0, 21, 4):
+        for k in (0, 1, (1 << m) // 3, (1 << m) - 1):
+            lons.append(-180.0 + 360.0 * k / 2.0 ** m)
+            want.append(k / 2.0 ** m)
+    X, _ = oracle.project(np.stack([lons, np.zeros(len(lons))], 1), lib_path)
+    assert np.array_equal(X, np.array(want)), "X not exact at dyadic longitudes"
+    lat_max = 85.0511287798066
+    lat_q = math.degrees(math.atan(math.sinh(math.pi / 2)))   # Y = 1/4 (z=2 row edge)
+    lats = np.array([0.0, lat_max, -lat_max, 89.0, -90.0, lat_q, -lat_q])
+    _, Y = oracle.project(np.stack([np.zeros(lats.size), lats], 1), lib_path)
+    assert abs(Y[0] - 0.5) <= 2e-16, Y[0]
+    assert abs(Y[1]) <= 1e-12 and abs(Y[2] - 1.0) <= 1e-12, (Y[1], Y[2])
+    assert Y[3] == Y[1] and Y[4] == Y[2], "latitude not clamped to the Mercator limit"
+    assert abs(Y[5] - 0.25) <= 1e-14 and abs(Y[6] - 0.75) <= 1e-14, (Y[5], Y[6])
+    grid = np.linspace(-85.0, 85.0, 17001)
+    _, Yg = oracle.project(np.stack([np.zeros(grid.size), grid], 1), lib_path)
+    assert np.all(np.diff(Yg) < 0), "Y must decrease strictly with latitude (y = 0 north)"
+    alt = 0.5 - np.arctanh(np.sin(np.radians(grid))) / (2 * math.pi)
+    assert np.max(np.abs(Yg - alt)) <= 2e-15, np.max(np.abs(Yg - alt))
+
+
+# ------------------------------------------------------------ addressing
+def pin_addressing(lib_path=None):
+    # Tile (0,0,0): pixel (i, j) centre is ((i+1/2)/256, (j+1/2)/256); row j = north-first.
+    i, j = 3, 200
+    ix = _ix([[(i + 0.5) / 256, (j + 0.5) / 256]], oracle.POINTS, lib_path=lib_path)
+    out = ix.render([[0, 0, 0]], 0.1)
+    lit = np.argwhere(out["bit"][0])
+    assert lit.tolist() == [[j, i]], lit.tolist()
+    # A northern-hemisphere point east of Greenwich is in tile (1,1,0).
+    ix = _ix([[10.0, 60.0], [-10.0, -60.0]], oracle.POINTS, merc01=False, lib_path=lib_path)
+    t = np.array([[1, 0, 0], [1, 1, 0], [1, 0, 1], [1, 1, 1]])
+    out = ix.render(t, 0.75)
+    n = out["bit"].reshape(4, -1).sum(1)
+    assert n[1] > 0 and n[2] > 0 and n[0] == 0 and n[3] == 0, n.tolist()
+    # Own pixel at random zooms (r >= sqrt(2)/2 covers the whole pixel).
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        z = int(rng.integers(0, 18))
+        X, Y = rng.uniform(0.01, 0.99, 2)
+        S = 256.0 * 2.0 ** z
+        gx, gy = int(X * S), int(Y * S)
+        tx, ty = gx // 256, gy // 256
+        ix = _ix([[X, Y]], oracle.POINTS, lib_path=lib_path)
+        out = ix.render([[z, tx, ty]], 0.75)
+        assert out["bit"][0][gy - 256 * ty, gx - 256 * tx] == 1, (z, X, Y)
+
+
+# ------------------------------------------------------------ lattice disks
+def _lattice_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "lattice_counts.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                pos, r, b, l, a = line.split()
+                rows.append((pos, float(r), int(b), int(l), int(a)))
+    return rows
+
+
+def pin_lattice(lib_path=None):
+    z, x, y = 10, 300, 400
+    for pos, r, nb, nl, na in _lattice_rows():
+        off = 0.5 if pos == "centre" else 0.0
+        for (pu, pv) in ((100 + off, 50 + off), (off, 50 + off)):   # interior, west seam
+            X, Y = _px_to_merc(z, x, y, pu, pv)
+            ix = _ix([[X, Y]], oracle.POINTS, lib_path=lib_path)
+            out = ix.render([[z, x, y], [z, x - 1, y]], r)
+            got = tuple(a + b for a, b in zip(_counts(out, 0), _counts(out, 1)))
+            assert got == (nb, nl, na), (pos, r, pu, got, (nb, nl, na))
+    # Band edges: a point at distance r + delta east of pixel (100, 50)'s centre,
+    # delta an exact dyadic offset; |delta| <= 1e-6 px is ambiguous, beyond is certain.
+    r = 2.0
+    for delta, tri_want, bit_want in ((2.0 ** -21, 2, 0), (-2.0 ** -21, 2, 1),
+                                      (2.0 ** -19, 0, 0), (-2.0 ** -19, 1, 1)):
+        X, Y = _px_to_merc(z, x, y, 100.5 + r + delta, 50.5)
+        out = _ix([[X, Y]], oracle.POINTS, lib_path=lib_path).render([[z, x, y]], r)
+        got = (int(out["tri"][0][50, 100]), int(out["bit"][0][50, 100]))
+        assert got == (tri_want, bit_want), (delta, got)
+
+
+# ------------------------------------------------------------ segments
+def pin_segments(lib_path=None):
+    z, x, y = 12, 1000, 2000
+    a, b, j = 20, 60, 77
+    L = b - a + 1
+    horiz = _seg(z, x, y, a + 0.5, j + 0.5, b + 0.5, j + 0.5)
+    vert = _seg(z, x, y, j + 0.5, a + 0.5, j + 0.5, b + 0.5)
+    for s in (horiz, vert):
+        ix = _ix(s, oracle.SEGMENTS, lib_path=lib_path)
+        out = ix.render([[z, x, y]], 0.5)
+        assert _counts(out) == (L, L, 0), _counts(out)
+        out = ix.render([[z, x, y]], 1.0)
+        assert _counts(out) == (3 * L + 2, L, 2 * L + 2), _counts(out)
+    # A segment on the boundary between rows j-1 and j: both rows at exactly 0.5.
+    ix = _ix(_seg(z, x, y, a + 0.5, j, b + 0.5, j), oracle.SEGMENTS, lib_path=lib_path)
+    out = ix.render([[z, x, y]], 0.5)
+    assert _counts(out) == (2 * L, 0, 2 * L), _counts(out)
+    # Diagonal through 21 centres; side neighbours at sqrt(2)/2.
+    ix = _ix(_seg(z, x, y, 10.5, 10.5, 30.5, 30.5), oracle.SEGMENTS, lib_path=lib_path)
+    out = ix.render([[z, x, y]], 0.5)
+    assert _counts(out) == (21, 21, 0), _counts(out)
+    out = ix.render([[z, x, y]], math.sqrt(2) / 2)
+    assert _counts(out)[1:] == (21, 40), _counts(out)
+    # End caps: distance is to the closed segment, not to its line.
+    ix = _ix(horiz, oracle.SEGMENTS, lib_path=lib_path)
+    out = ix.render([[z, x, y]], 2.0)
+    tri = out["tri"][0]
+    assert tri[j, b + 3] == 0 and tri[j, b + 2] == 2 and tri[j + 1, b + 1] == 1
+    assert tri[j, a - 3] == 0 and tri[j, a - 2] == 2 and tri[j - 1, a - 1] == 1
+    # Zero-length segment == point; segment mask contains its endpoints' masks.
+    rng = np.random.default_rng(5)
+    for r in (0.5, 1.3, 2.5):
+        u = rng.uniform(5, 250, (8, 2))
+        pts = np.stack(_px_to_merc(z, x, y, u[:, 0], u[:, 1]), 1)
+        o_pt = _ix(pts, oracle.POINTS, lib_path=lib_path).render([[z, x, y]], r)
+        o_sg = _ix(np.concatenate([pts, pts], 1), oracle.SEGMENTS,
+                   lib_path=lib_path).render([[z, x, y]], r)
+        assert np.array_equal(o_pt["tri"], o_sg["tri"]), r
+        s = np.concatenate([pts[:4], pts[4:]], 1)
+        o_s = _ix(s, oracle.SEGMENTS, lib_path=lib_path).render([[z, x, y]], r)
+        assert np.all(o_s["bit"] >= o_pt["bit"]), r
+
+
+# ------------------------------------------------------------ kinds
+def pin_kinds(lib_path=None):
+    rng = np.random.default_rng(7)
+    z, x, y = 9, 100, 150
+    k = 40
+    ang = np.sort(rng.uniform(0, 2 * math.pi, k))
+    rad = rng.uniform(30, 90, k)
+    u = 128 + rad * np.cos(ang)
+    v = 128 + rad * np.sin(ang)
+    P = np.stack(_px_to_merc(z, x, y, u, v), 1)
+    ring = np.concatenate([P, np.roll(P, -1, axis=0)], 1)      # k edges, closing included
+    for r in (0.5, 1.5):
+        a = _ix(ring, oracle.SEGMENTS, lib_path=lib_path).render([[z, x, y]], r)
+        b = _ix(ring, oracle.POLYGON_EDGES, lib_path=lib_path).render([[z, x, y]], r)
+        assert np.array_equal(a["tri"], b["tri"]) and np.array_equal(a["bit"], b["bit"])
+        pts = _ix(P, oracle.POINTS, lib_path=lib_path).render([[z, x, y]], r)
+        assert np.all(b["bit"] >= pts["bit"]) and b["bit"].sum() > pts["bit"].sum()
+
+
+# ------------------------------------------------------------ brute force
+def _random_objects(rng, kind, z, x, y, n, spread=10.0):
+    """Objects within the tile +- spread px (many straddle the seams)."""
+    u0 = rng.uniform(-spread, 256 + spread, (n, 2))
+    if kind == oracle.POINTS:
+        X, Y = _px_to_merc(z, x, y, u0[:, 0], u0[:, 1])
+        return np.stack([X, Y], 1)
+    d = rng.normal(0, 6.0, (n, 2)) * rng.choice([0.1, 1.0, 5.0], (n, 1))
+    u1 = u0 + d
+    if n >= 4:
+        u1[0] = u0[0]                                        # a zero-length segment
+    A = np.stack(_px_to_merc(z, x, y, u0[:, 0], u0[:, 1]), 1)
+    B = np.stack(_px_to_merc(z, x, y, u1[:, 0], u1[:, 1]), 1)
+    return np.concatenate([A, B], 1)
+
+
+def _check_against_brute(out, t, objs, kind, tile, r):
+    D = brute_distance(objs, kind if kind == 0 else 1, *tile)
+    want = tri_state(D, r)
+    ok = (out["tri"][t] == want) | near_band_edge(D, r)
+    assert ok.all(), (tile, r, int((~ok).sum()))
+    bit = D <= r
+    okb = (out["bit"][t].astype(bool) == bit) | near_band_edge(D, r)
+    assert okb.all(), (tile, r, int((~okb).sum()))
+    if "dist" in out:
+        sel = (out["tri"][t] != 1) & (D <= r + 1e-5 - 1e-9)
+        assert np.allclose(out["dist"][t][sel], D[sel], rtol=0, atol=1e-9)
+
+
+def pin_brute(lib_path=None, n_obj=160, seed=13):
+    rng = np.random.default_rng(seed)
+    for kind in (oracle.POINTS, oracle.SEGMENTS, oracle.POLYGON_EDGES):
+        for z in (3, 12):
+            x = int(rng.integers(1, (1 << z) - 1))
+            y = int(rng.integers(1, (1 << z) - 1))
+            objs = _random_objects(rng, kind, z, x, y, n_obj)
+            ix = _ix(objs, kind, lib_path=lib_path)
+            tiles = [(z, x, y), (z, x + 1, y), (z, x, y - 1)]
+            rs = rng.choice([0.5, 0.7, 1.0, 2.0, 2.5], 3)
+            out = ix.render(np.array(tiles), rs, want_dist=True)
+            for t, tile in enumerate(tiles):
+                _check_against_brute(out, t, objs, kind, tile, float(rs[t]))
+    # lon/lat input: the brute force projects with its own formula.
+    lonlat = np.stack([rng.uniform(10.0, 10.6, 100), rng.uniform(45.0, 45.4, 100)], 1)
+    ix = _ix(lonlat, oracle.POINTS, merc01=False, lib_path=lib_path)
+    m = objects_merc01(lonlat, 0)
+    z = 10
+    S = 2.0 ** z
+    tile = (z, int(m[0, 0] * S), int(m[0, 1] * S))
+    out = ix.render(np.array([tile]), 1.5, want_dist=True)
+    _check_against_brute(out, 0, m, 0, tile, 1.5)
+
+
+# ------------------------------------------------------------ cKDTree
+def pin_ckdtree(lib_path=None, n_tiles=256):
+    from scipy.spatial import cKDTree
+    import hvgen
+    pts = hvgen.gen_c1_points()
+    tiles, r = hvgen.c1_requests()
+    tiles = tiles[:n_tiles]
+    ix = oracle.OracleIndex(pts, oracle.POINTS, lib_path=lib_path)
+    out = ix.render(tiles, r)
+    z = 4
+    S = 256.0 * 2 ** z
+    m = objects_merc01(pts, 0) * S
+    kd = cKDTree(m)
+    c = np.arange(256) + 0.5
+    for t, (tz, tx, ty) in enumerate(tiles):
+        q = np.stack([np.tile(c, 256) + 256.0 * tx, np.repeat(c, 256) + 256.0 * ty], 1)
+        D, _ = kd.query(q, k=1, workers=-1)
+        D = D.reshape(256, 256)
+        want = tri_state(D, r)
+        ok = (out["tri"][t] == want) | near_band_edge(D, r, tol=1e-8)
+        assert ok.all(), (t, int((~ok).sum()))
+
+
+# ------------------------------------------------------------ invariants
+def pin_invariants(lib_path=None):
+    rng = np.random.default_rng(17)
+    z, x, y = 11, 700, 900
+    tiles = np.array([[z, x, y], [z, x + 1, y]])
+    for kind in (oracle.POINTS, oracle.SEGMENTS):
+        A = _random_objects(rng, kind, z, x, y, 120)
+        B = _random_objects(rng, kind, z, x, y, 120)
+        for r in (0.5, 1.0, 2.5):
+            oa = _ix(A, kind, lib_path=lib_path).render(tiles, r)
+            ob = _ix(B, kind, lib_path=lib_path).render(tiles, r)
+            AB = np.concatenate([A, B])
+            oab = _ix(AB, kind, lib_path=lib_path).render(tiles, r)
+            assert np.array_equal(oab["bit"], oa["bit"] | ob["bit"]), ("union", kind, r)
+            perm = rng.permutation(AB.shape[0])
+            op = _ix(AB[perm], kind, lib_path=lib_path).render(tiles, r)
+            assert np.array_equal(op["bit"], oab["bit"]) and np.array_equal(op["tri"], oab["tri"])
+        # monotone in r
+        ix = _ix(A, kind, lib_path=lib_path)
+        prev = None
+        for r in (0.3, 0.5, 0.75, 1.0, 1.7, 2.5, 4.0):
+            cur = ix.render(tiles, r)["bit"]
+            if prev is not None:
+                assert np.all(cur >= prev), ("monotone", kind, r)
+            prev = cur
+    # parent-empty => child-empty for r >= sqrt(2)/2, same r in px at both zooms
+    for kind in (oracle.POINTS, oracle.SEGMENTS):
+        pz, px_, py_ = 8, 90, 120
+        objs = _random_objects(rng, kind, pz, px_, py_, 60, spread=4.0)
+        ix = _ix(objs, kind, lib_path=lib_path)
+        kids = np.array([[pz + 1, 2 * px_ + a, 2 * py_ + b] for b in (0, 1) for a in (0, 1)])
+        for r in (1.0, 2.5):
+            par = ix.render([[pz, px_, py_]], r)["bit"][0]
+            ch = ix.render(kids, r)["bit"]
+            for k, (a, b) in enumerate([(0, 0), (1, 0), (0, 1), (1, 1)]):
+                for q in range(2):
+                    for s in range(2):
+                        sub = ch[k][q::2, s::2]            # child rows 2j'+q, cols 2i'+s
+                        parent = par[128 * b:128 * b + 128, 128 * a:128 * a + 128]
+                        assert np.all(sub <= parent), ("parent-empty", kind, r, a, b)
+    # tile translation: shifting by one tile width in X (exact on a dyadic grid)
+    z, x, y = 7, 40, 50
+    grid = 2.0 ** -30
+    for kind in (oracle.POINTS, oracle.SEGMENTS):
+        objs = np.round(_random_objects(rng, kind, z, x, y, 80) / grid) * grid
+        sh = objs.copy()
+        sh[:, 0::2] += 2.0 ** -z
+        o1 = _ix(objs, kind, lib_path=lib_path).render([[z, x, y]], 1.5)
+        o2 = _ix(sh, kind, lib_path=lib_path).render([[z, x + 1, y]], 1.5)
+        assert np.array_equal(o1["tri"], o2["tri"]), ("translation", kind)
+
+
+PINS = {
+    "projection": pin_projection,
+    "addressing": pin_addressing,
+    "lattice": pin_lattice,
+    "segments": pin_segments,
+    "kinds": pin_kinds,
+    "brute": pin_brute,
+    "invariants": pin_invariants,
+}

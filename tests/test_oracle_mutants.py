@@ -1,0 +1,51 @@
+"""Plants plausible mistakes in a copy of the oracle (on the CPU) and checks
+that at least one pin fails for each.  The oracle's own source is untouched."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hv_oracle.c")
+RUNNER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_mutant_runner.py")
+
+# (name, text in the oracle, planted replacement)
+MUTANTS = [
+    ("corner-sample", "const double px = i + 0.5, py = j + 0.5;", "const double px = i, py = j;"),
+    ("rows-south-first", "size_t p = (size_t)j * 256 + (size_t)i;",
+     "size_t p = (size_t)(255 - j) * 256 + (size_t)i;"),
+    ("transposed", "size_t p = (size_t)j * 256 + (size_t)i;", "size_t p = (size_t)i * 256 + (size_t)j;"),
+    ("y-sign", "*Y = 0.5 - log(", "*Y = 0.5 + log("),
+    ("no-lat-clamp", "if (lat > OR_MAX_LAT) lat = OR_MAX_LAT;", ""),
+    ("deg-to-rad", "double phi = lat * (OR_PI / 180.0);", "double phi = lat * (OR_PI / 360.0);"),
+    ("x-scale", "*X = (lon + 180.0) / 360.0;", "*X = (lon + 180.0) / 380.0;"),
+    ("no-end-clamp", "if (t > 1.0) t = 1.0;", ""),
+    ("strict-compare", "int b = D <= r;", "int b = D < r;"),
+    ("node-box-max-x", "if (c->x1 > b.x1) b.x1 = c->x1;", ""),
+    ("query-box-half-r", "const double h = r + OR_QUERY_PAD;", "const double h = 0.5 * r + OR_QUERY_PAD;"),
+    ("no-tile-offset", "const double ox = 256.0 * (double)tx,", "const double ox = 0.0 * (double)tx,"),
+    ("zoom-off-by-one", "const double S = 256.0 * ldexp(1.0, z);", "const double S = 256.0 * ldexp(1.0, z + 1);"),
+    ("point-d-squared", "return sqrt(ex * ex + ey * ey);\n    }\n    double bx",
+     "return ex * ex + ey * ey;\n    }\n    double bx"),
+    ("proj-sign", "t = ((px - ax) * dx + (py - ay) * dy) / len2;", "t = ((px - ax) * dx - (py - ay) * dy) / len2;"),
+    ("band-label", "(D > r + OR_BAND ? 0 : 2)", "(D > r ? 0 : 2)"),
+    ("early-exit", "if (D < r - OR_BAND) { certain = 1; break; }", "if (D < r + 1.0) { certain = 1; break; }"),
+    ("str-child-ids", "ix->child[*n_child + k] = e[s + k].id;", "ix->child[*n_child + k] = e[s].id;"),
+    ("edges-as-points", "if (ix->kind == OR_POINTS) {\n        double ex", "if (ix->kind != OR_SEGMENTS) {\n        double ex"),
+    ("segment-b-is-a", "ix->bx[q] = (w == 4) ? o[2] : o[0];", "ix->bx[q] = o[0];"),
+    ("box-meets-axis", "b->y0 <= a->y1;", "b->y0 <= a->x1;"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique/found: {name}"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    sys.path.insert(0, ROOT)
+    from oracle import build as ob
+    lib = ob.build(str(mut), str(tmp_path / "libmut.so"))
+    res = subprocess.run([sys.executable, RUNNER, lib], capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0, f"planted mistake {name!r} was not caught:\n{res.stdout}{res.stderr}"
