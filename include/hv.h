@@ -1,0 +1,160 @@
+/*
+ * hv.h -- per-pixel tile masks from spatial-index queries on MI355X (gfx950).
+ *
+ * Display-driven computing after HiVision (arXiv 2005.12489): every pixel of
+ * a 256x256 Web-Mercator tile is an independent unit of work, and its value
+ * comes from index queries about the objects near it (Sec. 1 and Sec. 3).
+ * This library computes the binary form of the paper's Algorithm 1 (SIBV):
+ * pixel (i, j) of tile (z, x, y) is lit iff some indexed point, segment or
+ * polygon edge lies within r pixels of the pixel's centre, where the
+ * distance is Euclidean in world pixels of zoom z (one pixel is the
+ * resolution R_z of Algorithm 1 and the style radius is R = N * R_z), and
+ * the comparison is inclusive.
+ *
+ * Conventions used by every entry point:
+ *   - Space: Web-Mercator normalised to [0,1]^2 with y = 0 at the north edge;
+ *     latitude is clamped to +-85.0511287798066 deg; there is no
+ *     antimeridian wrap.  Zoom z has 4^z tiles (XYZ scheme, rows from the
+ *     north, Sec. 2.1 and Sec. 4) of 256x256 pixels.
+ *   - Masks: one tile is 8192 bytes, row-major from the north-west pixel,
+ *     32 bytes per row; pixel column i is bit (i & 7), least significant
+ *     first, of byte (i >> 3) of its row.  Masks are fully overwritten.
+ *   - Precision: coordinates, distances and comparisons are FP64.
+ *   - Work is issued asynchronously on the calling thread's current stream
+ *     (hv_set_stream; default: the null stream).  Device outputs are valid
+ *     once that stream has reached the call.
+ *   - Errors: every call validates its arguments on the host before any
+ *     device work; on error nothing is launched, outputs are untouched, a
+ *     negative status is returned (NULL for hv_index_build) and
+ *     hv_last_error() describes the problem.  All entry points are
+ *     thread-safe; the error message and current stream are per thread.
+ */
+#ifndef HV_H
+#define HV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Index kinds (Sec. 3.1: RtreeP for points, RtreeL for linestring segments,
+ * RtreeE for polygon edges; linestrings and polygons are split into segments
+ * and edges before indexing). */
+enum {
+    HV_POINTS = 0,
+    HV_SEGMENTS = 1,
+    HV_POLYGON_EDGES = 2,
+    /* OR-ed into kind: inputs are already normalised Mercator X,Y. */
+    HV_INPUT_MERC01 = 0x100
+};
+
+enum { HV_OK = 0, HV_EINVAL = -1, HV_ENOMEM = -2, HV_EHIP = -3 };
+
+/* Largest zoom accepted; 1 ulp of a world coordinate at z = 22 is 2.4e-7 px. */
+#define HV_MAX_ZOOM 22
+/* Largest style radius / half-width, px. */
+#define HV_MAX_RADIUS 64.0
+/* Largest object count (sorted positions are 32-bit). */
+#define HV_MAX_OBJECTS 2000000000LL
+#define HV_MASK_BYTES 8192
+
+typedef struct hv_index hv_index;
+
+/* A tile request in the XYZ scheme: 0 <= z <= HV_MAX_ZOOM, 0 <= x, y < 2^z. */
+typedef struct { int32_t z, x, y, pad; } hv_tile;
+
+/* Style: point radius, or line / edge half-width (= width / 2), in pixels;
+ * 0 < r_px <= HV_MAX_RADIUS (Algorithm 1's radius N). */
+typedef struct { double r_px; } hv_style;
+
+/* Build an index over `n` objects (Sec. 3.1 data organisation; the paper's
+ * R-trees are replaced by a Hilbert-packed R-tree built on the GPU).
+ *   objects  device pointer owned by the caller, FP64 array-of-structures:
+ *            points (n,2) = lon, lat; segments / edges (n,4) =
+ *            lon0, lat0, lon1, lat1 (degrees; with HV_INPUT_MERC01 the
+ *            values are normalised X, Y instead).  Polygon rings arrive as
+ *            their edges, the closing edge included.  Only read during the
+ *            call; the caller may free it once the call returns.
+ *   kind     HV_POINTS, HV_SEGMENTS or HV_POLYGON_EDGES, optionally
+ *            | HV_INPUT_MERC01.
+ *   n        0 <= n <= HV_MAX_OBJECTS; n = 0 builds an empty index whose
+ *            masks are all zero.
+ * Synchronous.  Returns an index that owns all of its device memory and is
+ * immutable (renders on several streams may share it), or NULL: HV_EINVAL
+ * for a NULL pointer with n > 0, a bad kind or n, a non-finite coordinate,
+ * |lon| > 180 or |lat| > 90; HV_ENOMEM when device memory runs out; HV_EHIP
+ * for another HIP error. */
+hv_index *hv_index_build(const double *objects, int kind, int64_t n);
+
+/* Render the masks of `n_tiles` tiles of one index with one style
+ * (Algorithm 1 per pixel, binary form).  One launch covers every tile.
+ *   tiles      host array of n_tiles requests (copied during the call).
+ *   style      host pointer.
+ *   out_masks  device buffer of n_tiles * 8192 bytes owned by the caller; it
+ *              must not alias the index.  Tile k's mask is at k * 8192.
+ * Tiles that miss the data's bounding box (grown by r) come out all zero
+ * without a traversal (Sec. 4.1: such tiles create no task).
+ * Returns HV_OK, or HV_EINVAL for a NULL index/style/pointer with
+ * n_tiles > 0, n_tiles < 0, z outside [0, 22], x or y outside [0, 2^z), or
+ * r_px not finite or outside (0, 64]; HV_EHIP on a launch failure. */
+int hv_render_tiles(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
+                    const hv_style *style, uint8_t *out_masks);
+
+/* Release an index and its device memory (NULL-safe).  The caller must make
+ * sure no render using it is still in flight. */
+void hv_free(hv_index *index);
+
+/* Message describing the calling thread's most recent error ("" if none). */
+const char *hv_last_error(void);
+
+/* Set the calling thread's stream (a hipStream_t; NULL = null stream). */
+int hv_set_stream(void *hip_stream);
+
+/* Launch shape of the query kernel; zero fields take the defaults. */
+typedef struct {
+    int32_t block;          /* pixel block per wavefront: 8 (1 px/lane) or 16 (4 px/lane) */
+    int32_t cand_cap;       /* LDS candidate capacity per wavefront, >= 64 */
+    int32_t waves_per_wg;   /* wavefronts per workgroup: 1, 2 or 4 */
+    int32_t xcd_remap;      /* 1: keep a tile's workgroups on one XCD; 0: off; default 1 */
+} hv_launch;
+
+/* hv_render_tiles with an explicit launch shape (autotuning and variant
+ * tests).  Every valid shape produces identical masks.  Extra HV_EINVAL
+ * cases: block not 8 or 16, cand_cap < 64 or > 4096, waves_per_wg not 1,
+ * 2 or 4, or a shape needing more than 64 KiB of LDS per workgroup. */
+int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
+                       const hv_style *style, uint8_t *out_masks, const hv_launch *launch);
+
+/* Facts about a built index. */
+typedef struct {
+    int32_t kind;           /* HV_POINTS / HV_SEGMENTS / HV_POLYGON_EDGES */
+    int32_t levels;         /* node levels, leaves = level 0 */
+    int64_t n;              /* objects */
+    int64_t nodes;          /* nodes over all levels */
+    int32_t leaf_size;      /* objects per leaf */
+    int32_t fanout;         /* children per inner node */
+    int32_t key_bits;       /* Hilbert order used for sorting (bits per axis) */
+    int32_t pad;
+    double root[4];         /* data bounding box: min X, min Y, max X, max Y (normalised) */
+    int64_t device_bytes;   /* device memory held by the index */
+    double build_ms;        /* wall time of hv_index_build */
+} hv_info;
+
+/* Fill *info.  Returns HV_OK or HV_EINVAL for a NULL argument. */
+int hv_index_info(const hv_index *index, hv_info *info);
+
+/* Copy one of the index's device arrays to host memory (synchronous; for
+ * tests and tools).  what: HV_READ_ORDER = sorted position -> input index
+ * (uint32, n entries); HV_READ_OBJECTS = projected objects in sorted order
+ * (FP64, n*2 or n*4); HV_READ_NODES = node boxes of `level` (FP64 min X,
+ * min Y, max X, max Y per node).  `bytes` must equal the array's size.
+ * Returns HV_OK, HV_EINVAL, or HV_EHIP. */
+enum { HV_READ_ORDER = 0, HV_READ_OBJECTS = 1, HV_READ_NODES = 2 };
+int hv_index_read(const hv_index *index, int what, int level, void *host_dst, int64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HV_H */

@@ -1,0 +1,222 @@
+"""Python binding of the tile-mask C ABI (include/hv.h): marshalling only.
+
+Every entry point of the library has a function of the same name here; each
+converts its arguments (torch tensors, numpy arrays, Python numbers) to the
+C types, sets the library's stream to torch's current stream, calls the
+library and turns a negative status into ``HvError``.  All computation runs
+in the HIP kernels of ``libhv.so``; if that library is missing, importing
+this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhv.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2005_12489_amd/build.py "
+                      "(or __graft_entry__.build()) first")
+
+HV_POINTS, HV_SEGMENTS, HV_POLYGON_EDGES = 0, 1, 2
+HV_INPUT_MERC01 = 0x100
+HV_OK, HV_EINVAL, HV_ENOMEM, HV_EHIP = 0, -1, -2, -3
+HV_READ_ORDER, HV_READ_OBJECTS, HV_READ_NODES = 0, 1, 2
+HV_MASK_BYTES = 8192
+HV_MAX_ZOOM = 22
+
+SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free", "hv_last_error",
+           "hv_set_stream", "hv_index_info", "hv_index_read")
+
+
+class hv_tile(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_int32), ("x", ctypes.c_int32), ("y", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class hv_style(ctypes.Structure):
+    _fields_ = [("r_px", ctypes.c_double)]
+
+
+class hv_launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
+                ("waves_per_wg", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+
+class hv_info(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("levels", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("nodes", ctypes.c_int64), ("leaf_size", ctypes.c_int32), ("fanout", ctypes.c_int32),
+                ("key_bits", ctypes.c_int32), ("pad", ctypes.c_int32), ("root", ctypes.c_double * 4),
+                ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
+
+
+class HvError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{code}: {message}")
+        self.code = code
+
+
+_P = ctypes.c_void_p
+lib = ctypes.CDLL(LIB_PATH)
+lib.hv_index_build.restype = _P
+lib.hv_index_build.argtypes = [_P, ctypes.c_int, ctypes.c_int64]
+lib.hv_render_tiles.restype = ctypes.c_int
+lib.hv_render_tiles.argtypes = [_P, _P, ctypes.c_int64, ctypes.POINTER(hv_style), _P]
+lib.hv_render_tiles_ex.restype = ctypes.c_int
+lib.hv_render_tiles_ex.argtypes = [_P, _P, ctypes.c_int64, ctypes.POINTER(hv_style), _P,
+                                   ctypes.POINTER(hv_launch)]
+lib.hv_free.restype = None
+lib.hv_free.argtypes = [_P]
+lib.hv_last_error.restype = ctypes.c_char_p
+lib.hv_last_error.argtypes = []
+lib.hv_set_stream.restype = ctypes.c_int
+lib.hv_set_stream.argtypes = [_P]
+lib.hv_index_info.restype = ctypes.c_int
+lib.hv_index_info.argtypes = [_P, ctypes.POINTER(hv_info)]
+lib.hv_index_read.restype = ctypes.c_int
+lib.hv_index_read.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64]
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise HvError(rc, hv_last_error())
+    return rc
+
+
+def _device_ptr(t):
+    """A torch tensor's device address, or an int address as given."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _sync_stream():
+    """Points the library at torch's current stream (if torch has a GPU)."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        return
+    if torch.cuda.is_available() and torch.cuda.is_initialized():
+        lib.hv_set_stream(torch.cuda.current_stream().cuda_stream)
+
+
+def tiles_array(tiles) -> np.ndarray:
+    """(n,3) or (n,4) integers z, x, y[, pad] -> contiguous (n,4) int32."""
+    t = np.asarray(tiles, dtype=np.int64).reshape(-1, np.shape(tiles)[-1] if np.ndim(tiles) > 1 else 3)
+    out = np.zeros((t.shape[0], 4), dtype=np.int32)
+    if t.size and (t[:, :3].min() < np.iinfo(np.int32).min or t[:, :3].max() > np.iinfo(np.int32).max):
+        raise HvError(HV_EINVAL, "tile coordinates do not fit int32")
+    out[:, :3] = t[:, :3]
+    return out
+
+
+# ------------------------------------------------------------ entry points
+def hv_last_error() -> str:
+    return lib.hv_last_error().decode()
+
+
+def hv_set_stream(stream) -> None:
+    """stream: a torch.cuda.Stream, a raw hipStream_t address, or None."""
+    ptr = getattr(stream, "cuda_stream", stream)
+    _check(lib.hv_set_stream(ptr))
+
+
+def hv_index_build(objects, kind: int, n: int | None = None) -> int:
+    """objects: float64 device tensor (n,2) or (n,4), or a device address
+    (then n is required).  Returns the opaque index handle."""
+    if n is None:
+        n = int(objects.shape[0])
+    if hasattr(objects, "dtype") and n > 0:
+        if str(objects.dtype) != "torch.float64" or not objects.is_contiguous():
+            raise HvError(HV_EINVAL, "objects must be a contiguous float64 tensor")
+    _sync_stream()
+    h = lib.hv_index_build(_device_ptr(objects), int(kind), int(n))
+    if not h:
+        raise HvError(HV_EINVAL, hv_last_error())
+    return h
+
+
+def hv_render_tiles(index: int, tiles, style, out_masks) -> None:
+    """tiles: (n,3)/(n,4) ints; style: r in px (float) or hv_style;
+    out_masks: uint8 device tensor of n*8192 bytes (or a device address)."""
+    t = tiles_array(tiles)
+    st = style if isinstance(style, hv_style) else hv_style(float(style))
+    _sync_stream()
+    _check(lib.hv_render_tiles(index, t.ctypes.data_as(_P), t.shape[0], ctypes.byref(st),
+                               _device_ptr(out_masks)))
+
+
+def hv_render_tiles_ex(index: int, tiles, style, out_masks, launch: hv_launch | dict | None) -> None:
+    t = tiles_array(tiles)
+    st = style if isinstance(style, hv_style) else hv_style(float(style))
+    if isinstance(launch, dict):
+        launch = hv_launch(**launch)
+    _sync_stream()
+    _check(lib.hv_render_tiles_ex(index, t.ctypes.data_as(_P), t.shape[0], ctypes.byref(st),
+                                  _device_ptr(out_masks), ctypes.byref(launch) if launch else None))
+
+
+def hv_free(index: int | None) -> None:
+    lib.hv_free(index)
+
+
+def hv_index_info(index: int) -> dict:
+    info = hv_info()
+    _check(lib.hv_index_info(index, ctypes.byref(info)))
+    d = {k: getattr(info, k) for k, _ in hv_info._fields_ if k not in ("pad", "root")}
+    d["root"] = list(info.root)
+    return d
+
+
+def hv_index_read(index: int, what: int, level: int = 0) -> np.ndarray:
+    info = hv_index_info(index)
+    w = 2 if info["kind"] == HV_POINTS else 4
+    if what == HV_READ_ORDER:
+        out = np.empty(info["n"], dtype=np.uint32)
+    elif what == HV_READ_OBJECTS:
+        out = np.empty((info["n"], w), dtype=np.float64)
+    elif what == HV_READ_NODES:
+        # the level's node count is implicit in the tree shape
+        cnt = -(-info["n"] // info["leaf_size"])
+        for _ in range(level):
+            cnt = -(-cnt // info["fanout"])
+        out = np.empty((cnt, 4), dtype=np.float64)
+    else:
+        raise HvError(HV_EINVAL, "unknown array")
+    _check(lib.hv_index_read(index, what, level, out.ctypes.data_as(_P), out.nbytes))
+    return out
+
+
+# ------------------------------------------------------------ convenience
+class Index:
+    """Owns one index handle; frees it when collected."""
+
+    def __init__(self, objects, kind: int):
+        self.kind = kind
+        self.handle = hv_index_build(objects, kind)
+
+    def render(self, tiles, r, out=None, launch=None):
+        """Returns (or fills) a uint8 device tensor (n, 8192) of masks."""
+        import torch
+        t = tiles_array(tiles)
+        if out is None:
+            out = torch.empty((t.shape[0], HV_MASK_BYTES), dtype=torch.uint8, device="cuda")
+        if launch is None:
+            hv_render_tiles(self.handle, t, r, out)
+        else:
+            hv_render_tiles_ex(self.handle, t, r, out, launch)
+        return out
+
+    def info(self) -> dict:
+        return hv_index_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            hv_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

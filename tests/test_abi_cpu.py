@@ -1,0 +1,86 @@
+"""The C-ABI library loads, exports every symbol include/hv.h declares, and
+rejects bad arguments on the host before any device call (no GPU needed)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hv.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hv_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def hv():
+    from paper_2005_12489_amd import hv as m
+    return m
+
+
+def test_every_declared_symbol_is_exported(hv):
+    names = _declared()
+    assert "hv_index_build" in names and "hv_render_tiles" in names and "hv_free" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", hv.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (hv_[a-z_]+)\b", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert set(hv.SYMBOLS) == set(names)
+
+
+def test_build_rejects_bad_arguments(hv):
+    for args, msg in [((None, 7, 3), "unknown kind"), ((None, 0x200, 3), "unknown kind"),
+                      ((None, 0, 3), "NULL"), ((None, 0, -1), "n outside"),
+                      ((None, 1, 3_000_000_000), "n outside")]:
+        with pytest.raises(hv.HvError, match=msg) as e:
+            hv.hv_index_build(*args)
+        assert e.value.code == hv.HV_EINVAL
+    host = np.zeros((4, 2))
+    with pytest.raises(hv.HvError, match="device memory"):
+        hv.hv_index_build(host.ctypes.data, hv.HV_POINTS, 4)
+
+
+def test_empty_index_needs_no_device(hv):
+    h = hv.hv_index_build(None, hv.HV_SEGMENTS, 0)
+    info = hv.hv_index_info(h)
+    assert info["n"] == 0 and info["levels"] == 0 and info["device_bytes"] == 0
+    hv.hv_render_tiles(h, np.zeros((0, 3)), 1.0, 0)         # nothing to do
+    hv.hv_free(h)
+    hv.hv_free(None)
+
+
+@pytest.mark.parametrize("tile,r,msg", [
+    ((23, 0, 0), 1.0, "zoom"), ((-1, 0, 0), 1.0, "zoom"), ((3, 8, 0), 1.0, "x or y"),
+    ((3, 0, -1), 1.0, "x or y"), ((22, 1 << 22, 0), 1.0, "x or y"), ((3, 1, 1), 0.0, "r_px"),
+    ((3, 1, 1), -1.0, "r_px"), ((3, 1, 1), float("nan"), "r_px"), ((3, 1, 1), float("inf"), "r_px"),
+    ((3, 1, 1), 64.5, "r_px")])
+def test_render_rejects_bad_requests(hv, tile, r, msg):
+    h = hv.hv_index_build(None, hv.HV_POINTS, 0)
+    try:
+        with pytest.raises(hv.HvError, match=msg):
+            hv.hv_render_tiles(h, [tile], r, 1)              # a non-NULL dummy, never touched
+    finally:
+        hv.hv_free(h)
+
+
+def test_render_rejects_host_output_and_bad_shapes(hv):
+    h = hv.hv_index_build(None, hv.HV_POINTS, 0)
+    buf = np.zeros(8192, np.uint8)
+    try:
+        with pytest.raises(hv.HvError, match="device memory"):
+            hv.hv_render_tiles(h, [(3, 1, 1)], 1.0, buf.ctypes.data)
+        for bad in (dict(block=12), dict(cand_cap=32), dict(cand_cap=5000), dict(waves_per_wg=3),
+                    dict(waves_per_wg=8)):
+            with pytest.raises(hv.HvError, match="launch"):
+                hv.hv_render_tiles_ex(h, [(3, 1, 1)], 1.0, buf.ctypes.data, bad)
+        with pytest.raises(hv.HvError, match="NULL"):
+            hv.hv_render_tiles(h, [(3, 1, 1)], 1.0, 0)
+        assert (buf == 0).all()
+    finally:
+        hv.hv_free(h)
