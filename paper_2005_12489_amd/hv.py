@@ -14,11 +14,22 @@ import os
 
 import numpy as np
 
+# torch supplies device memory and streams, and ships its own HIP runtime.
+# It must be loaded first so that libhv.so binds to that same runtime (both
+# carry the soname libamdhip64.so.7); two runtimes in one process would not
+# recognise each other's allocations or streams.
+import torch  # noqa: F401,E402
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhv.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2005_12489_amd/build.py "
                       "(or __graft_entry__.build()) first")
+
+
+def _hip_runtimes() -> set:
+    with open("/proc/self/maps") as f:
+        return {ln.split()[-1] for ln in f if "libamdhip64" in ln and "/" in ln}
 
 HV_POINTS, HV_SEGMENTS, HV_POLYGON_EDGES = 0, 1, 2
 HV_INPUT_MERC01 = 0x100
@@ -59,6 +70,9 @@ class HvError(RuntimeError):
 
 _P = ctypes.c_void_p
 lib = ctypes.CDLL(LIB_PATH)
+if len(_hip_runtimes()) > 1:
+    raise ImportError(f"two HIP runtimes are loaded ({sorted(_hip_runtimes())}); "
+                      "libhv.so must share torch's")
 lib.hv_index_build.restype = _P
 lib.hv_index_build.argtypes = [_P, ctypes.c_int, ctypes.c_int64]
 lib.hv_render_tiles.restype = ctypes.c_int
