@@ -191,13 +191,17 @@ int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_ti
     if (index->device >= 0 && (hipGetDevice(&dev) != hipSuccess || dev != index->device))
         return fail(HV_EINVAL, "the current device is not the index's device");
 
-    hv::DevTile *d_tiles = nullptr;
-    hipError_t e = hipMallocAsync((void **)&d_tiles, sizeof(hv::DevTile) * n_tiles, t_stream);
+    // one stream-ordered allocation: the tile list, then the query's scratch
+    const size_t tile_bytes = (sizeof(hv::DevTile) * (size_t)n_tiles + 255) / 256 * 256;
+    unsigned char *d_buf = nullptr;
+    hipError_t e = hipMallocAsync((void **)&d_buf, tile_bytes + hv::query_scratch_bytes(n_tiles), t_stream);
     if (e != hipSuccess) return hip_status(e, "hv_render_tiles");
+    hv::DevTile *d_tiles = reinterpret_cast<hv::DevTile *>(d_buf);
     e = hipMemcpyAsync(d_tiles, tiles, sizeof(hv::DevTile) * n_tiles, hipMemcpyHostToDevice, t_stream);
     if (e == hipSuccess)
-        e = hv::launch_query_tiles(dev_view(index), d_tiles, n_tiles, style->r_px, out_masks, shape, t_stream);
-    const hipError_t ef = hipFreeAsync(d_tiles, t_stream);
+        e = hv::launch_query_tiles(dev_view(index), d_tiles, n_tiles, style->r_px, out_masks, shape,
+                                   d_buf + tile_bytes, t_stream);
+    const hipError_t ef = hipFreeAsync(d_buf, t_stream);
     if (e != hipSuccess) return hip_status(e, "hv_render_tiles");
     if (ef != hipSuccess) return hip_status(ef, "hv_render_tiles");
     t_err.clear();

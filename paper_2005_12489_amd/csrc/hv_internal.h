@@ -68,8 +68,12 @@ struct LaunchShape {
 // LDS bytes per workgroup for a shape (0 if the shape is invalid).
 size_t query_lds_bytes(const LaunchShape &s, int levels, int seg);
 
-// Launches the per-tile query kernel over `n_tiles` device tiles.
+// Device scratch the query needs for `n_tiles` tiles (per-tile frontiers).
+size_t query_scratch_bytes(int64_t n_tiles);
+
+// Launches the tile-frontier and query kernels over `n_tiles` device tiles;
+// `scratch` holds query_scratch_bytes(n_tiles) bytes of device memory.
 hipError_t launch_query_tiles(const DevIndex &ix, const DevTile *tiles, int64_t n_tiles, double r,
-                              uint8_t *out, const LaunchShape &s, hipStream_t stream);
+                              uint8_t *out, const LaunchShape &s, void *scratch, hipStream_t stream);
 
 }  // namespace hv
