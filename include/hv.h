@@ -91,13 +91,15 @@ hv_index *hv_index_build(const double *objects, int kind, int64_t n);
  * (Algorithm 1 per pixel, binary form).  One launch covers every tile.
  *   tiles      host array of n_tiles requests (copied during the call).
  *   style      host pointer.
- *   out_masks  device buffer of n_tiles * 8192 bytes owned by the caller; it
- *              must not alias the index.  Tile k's mask is at k * 8192.
+ *   out_masks  device buffer of n_tiles * 8192 bytes owned by the caller,
+ *              16-byte aligned; it must not alias the index.  Tile k's
+ *              mask is at k * 8192.
  * Tiles that miss the data's bounding box (grown by r) come out all zero
  * without a traversal (Sec. 4.1: such tiles create no task).
  * Returns HV_OK, or HV_EINVAL for a NULL index/style/pointer with
- * n_tiles > 0, n_tiles < 0, z outside [0, 22], x or y outside [0, 2^z), or
- * r_px not finite or outside (0, 64]; HV_EHIP on a launch failure. */
+ * n_tiles > 0, n_tiles < 0, z outside [0, 22], x or y outside [0, 2^z),
+ * r_px not finite or outside (0, 64], or out_masks not 16-byte aligned
+ * device memory; HV_EHIP on a launch failure. */
 int hv_render_tiles(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
                     const hv_style *style, uint8_t *out_masks);
 
@@ -113,16 +115,17 @@ int hv_set_stream(void *hip_stream);
 
 /* Launch shape of the query kernel; zero fields take the defaults. */
 typedef struct {
-    int32_t block;          /* pixel block per wavefront: 8 (1 px/lane) or 16 (4 px/lane) */
+    int32_t block;          /* pixel block per wavefront: 8, 16 or 32 (1, 4 or 16 px/lane) */
     int32_t cand_cap;       /* LDS candidate capacity per wavefront, >= 64 */
     int32_t waves_per_wg;   /* wavefronts per workgroup: 1, 2 or 4 */
-    int32_t xcd_remap;      /* 1: keep a tile's workgroups on one XCD; 0: off; default 1 */
+    int32_t grid_wgs;       /* workgroups of the persistent query kernel; 0 = as many as fit on the GPU */
 } hv_launch;
 
 /* hv_render_tiles with an explicit launch shape (autotuning and variant
  * tests).  Every valid shape produces identical masks.  Extra HV_EINVAL
- * cases: block not 8 or 16, cand_cap < 64 or > 4096, waves_per_wg not 1,
- * 2 or 4, or a shape needing more than 64 KiB of LDS per workgroup. */
+ * cases: block not 8, 16 or 32, cand_cap < 64 or > 4096, waves_per_wg not 1,
+ * 2 or 4, grid_wgs outside [0, 2^20], or a shape needing more than 64 KiB
+ * of LDS per workgroup. */
 int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
                        const hv_style *style, uint8_t *out_masks, const hv_launch *launch);
 

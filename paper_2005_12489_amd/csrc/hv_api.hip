@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "../../include/hv.h"
 #include "hv_internal.h"
@@ -76,23 +77,85 @@ int validate_style(const hv_style *style) {
     return HV_OK;
 }
 
-int resolve_shape(const hv_launch *l, const hv_index *ix, hv::LaunchShape *s) {
+int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s) {
     s->block = 16;
-    s->cand_cap = 128;
-    s->waves = 4;
-    s->xcd_remap = 1;
+    s->cand_cap = 64;
+    s->waves = 2;
+    s->grid = 0;
     if (l) {
         if (l->block) s->block = l->block;
         if (l->cand_cap) s->cand_cap = l->cand_cap;
         if (l->waves_per_wg) s->waves = l->waves_per_wg;
-        if (l->xcd_remap == 0) s->xcd_remap = 0;
+        s->grid = l->grid_wgs;
     }
-    if (s->block != 8 && s->block != 16) return fail(HV_EINVAL, "launch.block must be 8 or 16");
+    if (s->block != 8 && s->block != 16 && s->block != 32)
+        return fail(HV_EINVAL, "launch.block must be 8, 16 or 32");
     if (s->cand_cap < 64 || s->cand_cap > 4096) return fail(HV_EINVAL, "launch.cand_cap must be in [64, 4096]");
     if (s->waves != 1 && s->waves != 2 && s->waves != 4)
         return fail(HV_EINVAL, "launch.waves_per_wg must be 1, 2 or 4");
-    if (hv::query_lds_bytes(*s, ix->a.levels, ix->a.seg) > 65536)
+    if (s->grid < 0 || s->grid > (1 << 20)) return fail(HV_EINVAL, "launch.grid_wgs must be in [0, 2^20]");
+    if (hv::query_lds_bytes(*s, max_levels) > 65536)
         return fail(HV_EINVAL, "launch shape needs more than 64 KiB of LDS per workgroup");
+    return HV_OK;
+}
+
+// Per-thread pinned staging buffer for the host part of a workspace.  An
+// event guards it: it is only refilled once the previous copy from it has
+// completed.
+struct HostStage {
+    unsigned char *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    ~HostStage() {
+        if (pending) (void)hipEventSynchronize(ev);
+        if (ev) (void)hipEventDestroy(ev);
+        if (p) (void)hipHostFree(p);
+    }
+    hipError_t acquire(size_t bytes) {
+        if (pending) {
+            const hipError_t e = hipEventSynchronize(ev);
+            if (e != hipSuccess) return e;
+            pending = false;
+        }
+        if (!ev) {
+            const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        if (bytes > cap) {
+            if (p) (void)hipHostFree(p);
+            p = nullptr;
+            cap = 0;
+            const size_t want = bytes < 65536 ? 65536 : bytes + bytes / 2;
+            const hipError_t e = hipHostMalloc((void **)&p, want, hipHostMallocDefault);
+            if (e != hipSuccess) return e;
+            cap = want;
+        }
+        return hipSuccess;
+    }
+};
+thread_local HostStage t_stage;
+
+// Copies the staged workspace to a fresh stream-ordered device allocation
+// and launches the query; the allocation is released in stream order.
+int run_batch(const hv::DevIndex *ixs, int n_ix, int max_levels, const hv::DevReq *reqs, int64_t n_req,
+              uint8_t *out, const hv::LaunchShape &shape, const char *who) {
+    const hv::Workspace w = hv::workspace_layout(n_req, n_ix);
+    hipError_t e = t_stage.acquire(w.staged_bytes());
+    if (e != hipSuccess) return hip_status(e, who);
+    hv::stage_host(w, ixs, n_ix, reqs, n_req, t_stage.p);
+    unsigned char *dws = nullptr;
+    e = hipMallocAsync((void **)&dws, w.total, t_stream);
+    if (e != hipSuccess) return hip_status(e, who);
+    e = hipMemcpyAsync(dws, t_stage.p, w.staged_bytes(), hipMemcpyHostToDevice, t_stream);
+    if (e == hipSuccess) e = hipEventRecord(t_stage.ev, t_stream);
+    if (e == hipSuccess) {
+        t_stage.pending = true;
+        e = hv::launch_query(w, dws, n_req, max_levels, out, shape, t_stream);
+    }
+    const hipError_t ef = hipFreeAsync(dws, t_stream);
+    if (e != hipSuccess) return hip_status(e, who);
+    if (ef != hipSuccess) return hip_status(ef, who);
     return HV_OK;
 }
 
@@ -181,29 +244,22 @@ int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_ti
     if (n_tiles > 0 && (!tiles || !out_masks)) return fail(HV_EINVAL, "tiles or out_masks is NULL");
     if ((rc = validate_tiles(tiles, n_tiles))) return rc;
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, index, &shape))) return rc;
+    if ((rc = resolve_shape(launch, index->a.levels, &shape))) return rc;
     if (n_tiles == 0) {
         t_err.clear();
         return HV_OK;
     }
+    if (reinterpret_cast<uintptr_t>(out_masks) % 16 != 0) return fail(HV_EINVAL, "out_masks must be 16-byte aligned");
     if (!is_device_pointer(out_masks)) return fail(HV_EINVAL, "out_masks must be device memory");
     int dev = -1;
     if (index->device >= 0 && (hipGetDevice(&dev) != hipSuccess || dev != index->device))
         return fail(HV_EINVAL, "the current device is not the index's device");
-
-    // one stream-ordered allocation: the tile list, then the query's scratch
-    const size_t tile_bytes = (sizeof(hv::DevTile) * (size_t)n_tiles + 255) / 256 * 256;
-    unsigned char *d_buf = nullptr;
-    hipError_t e = hipMallocAsync((void **)&d_buf, tile_bytes + hv::query_scratch_bytes(n_tiles), t_stream);
-    if (e != hipSuccess) return hip_status(e, "hv_render_tiles");
-    hv::DevTile *d_tiles = reinterpret_cast<hv::DevTile *>(d_buf);
-    e = hipMemcpyAsync(d_tiles, tiles, sizeof(hv::DevTile) * n_tiles, hipMemcpyHostToDevice, t_stream);
-    if (e == hipSuccess)
-        e = hv::launch_query_tiles(dev_view(index), d_tiles, n_tiles, style->r_px, out_masks, shape,
-                                   d_buf + tile_bytes, t_stream);
-    const hipError_t ef = hipFreeAsync(d_buf, t_stream);
-    if (e != hipSuccess) return hip_status(e, "hv_render_tiles");
-    if (ef != hipSuccess) return hip_status(ef, "hv_render_tiles");
+    std::vector<hv::DevReq> reqs((size_t)n_tiles);
+    for (int64_t k = 0; k < n_tiles; ++k)
+        reqs[(size_t)k] = hv::DevReq{tiles[k].z, tiles[k].x, tiles[k].y, 0, style->r_px};
+    const hv::DevIndex ix = dev_view(index);
+    rc = run_batch(&ix, 1, index->a.levels, reqs.data(), n_tiles, out_masks, shape, "hv_render_tiles");
+    if (rc) return rc;
     t_err.clear();
     return HV_OK;
 }

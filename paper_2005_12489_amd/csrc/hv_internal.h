@@ -26,9 +26,11 @@ struct DevIndex {
     int32_t seg;                 // 0 points, 1 segments / edges
 };
 
-// A tile request as the kernels see it.
-struct DevTile {
-    int32_t z, x, y, pad;
+// A request as the kernels see it: one tile of one index with its own
+// radius / half-width.  `index` selects an entry of the batch's index table.
+struct DevReq {
+    int32_t z, x, y, index;
+    double r;
 };
 
 struct BuildResult {
@@ -60,20 +62,34 @@ void free_index_arrays(IndexArrays *a);
 
 struct LaunchShape {
     int block;        // 8 or 16
-    int cand_cap;     // candidates per wave
+    int cand_cap;     // staged candidates per wave
     int waves;        // waves per workgroup
-    int xcd_remap;    // 0/1
+    int grid;         // workgroups of the persistent query kernel (0: fill the GPU)
 };
 
-// LDS bytes per workgroup for a shape (0 if the shape is invalid).
-size_t query_lds_bytes(const LaunchShape &s, int levels, int seg);
+// LDS bytes per workgroup for a shape and the deepest index of a batch.
+size_t query_lds_bytes(const LaunchShape &s, int max_levels);
 
-// Device scratch the query needs for `n_tiles` tiles (per-tile frontiers).
-size_t query_scratch_bytes(int64_t n_tiles);
+// Device workspace of one batch of n requests over n_ix indexes.  The first
+// staged_bytes() bytes (index table, requests, a zeroed counter) are copied
+// from the host; the rest (frontiers, compacted tile list) is written by the
+// kernels.
+struct Workspace {
+    size_t table_off, req_off, counter_off, frontier_off, fmeta_off, list_off, total;
+    size_t staged_bytes() const { return frontier_off; }
+};
+Workspace workspace_layout(int64_t n_req, int n_ix);
 
-// Launches the tile-frontier and query kernels over `n_tiles` device tiles;
-// `scratch` holds query_scratch_bytes(n_tiles) bytes of device memory.
-hipError_t launch_query_tiles(const DevIndex &ix, const DevTile *tiles, int64_t n_tiles, double r,
-                              uint8_t *out, const LaunchShape &s, void *scratch, hipStream_t stream);
+// Fills the host part of a workspace (index table, requests, zero counter).
+void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq *reqs, int64_t n_req,
+                unsigned char *host);
+
+// Launches the tile-frontier and persistent query kernels for a staged
+// workspace `dws` (device) on `stream`.  Masks go to out + k * 8192.
+hipError_t launch_query(const Workspace &w, unsigned char *dws, int64_t n_req, int max_levels, uint8_t *out,
+                        const LaunchShape &s, hipStream_t stream);
+
+// Workgroups that fill the current device for a shape (occupancy x CUs).
+int persistent_grid(const LaunchShape &s, int max_levels);
 
 }  // namespace hv

@@ -1,23 +1,28 @@
 // Per-pixel tile-mask query (binary form of the paper's Algorithm 1).
 //
 // Display-driven computing makes each pixel a unit of work whose value comes
-// from index queries about nearby objects (Sec. 3).  On the GPU:
+// from index queries about nearby objects (Sec. 3).  A batch of requests --
+// each one tile of one index with its own radius -- runs as two kernels:
 //
-//  1. k_tile_frontier -- one wavefront per tile walks the tree breadth-first
-//     with the tile's box grown by r and keeps the deepest level at which at
-//     most 64 nodes meet it.  A tile whose frontier is empty misses all data
-//     and its blocks write zeros at once (Sec. 4.1: such tiles make no task).
-//  2. k_query_tiles -- one wavefront per square block of pixels (8x8, one
-//     pixel per lane, or 16x16, four per lane) starts from its tile's
-//     frontier and walks down with the block's box grown by r: the OuterBox
-//     filter of Algorithm 1, shared by the block's pixels.  Objects that pass
-//     are staged in LDS in tile-local pixel coordinates together with the
-//     range of block pixels their box grown by r covers.  Small ranges are
-//     tested object-parallel (one lane per object, only its own pixels: the
-//     per-pixel box filter of Algorithm 1 seen from the object's side);
-//     large ones pixel-parallel (every lane tests its own pixels).  Every
-//     test is the exact FP64 distance against r, inclusive.  Once every
-//     pixel of the block is lit the wavefront stops, as Algorithm 1 returns
+//  1. k_tile_frontier -- one wavefront per request walks the tree breadth-
+//     first with the tile's box grown by r and keeps the deepest level at
+//     which at most 256 nodes meet it.  A tile whose frontier is empty misses
+//     all data: it writes its zero mask here and takes no further work
+//     (Sec. 4.1: tiles outside the data's bounds make no task).  The others
+//     are appended to a compacted work list.
+//  2. k_query -- a persistent grid (as many workgroups as the GPU holds at
+//     once) strides over the (tile, pixel block) items of that list, one
+//     wavefront per block (8x8, 16x16 or 32x32: 1, 4 or 16 pixels per lane),
+//     the way the paper's engine hands tiles to idle processes (Sec. 4.3).
+//     A block starts from its tile's frontier and walks down with the
+//     block's box grown by r: the OuterBox filter of Algorithm 1, shared by
+//     the block's pixels.  Objects that pass are staged in LDS in tile-local
+//     pixel coordinates with the range of block pixels their box grown by r
+//     covers.  Small ranges are tested object-parallel (one lane per object,
+//     only its own pixels: Algorithm 1's per-pixel box filter seen from the
+//     object's side); large ones pixel-parallel (every lane its own pixels).
+//     Every test is the exact FP64 distance against r, inclusive.  Once all
+//     pixels of the block are lit the wavefront stops, as Algorithm 1 returns
 //     as soon as one object lies within the radius.
 //
 // The tree walk is wavefront-uniform: the stack lives in LDS, each step pops
@@ -25,58 +30,63 @@
 // children at once; hits are pushed with one ballot.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+#include <mutex>
+
 #include "hv_internal.h"
 
 namespace hv {
 namespace {
 
-constexpr int kFrontier = 64;             // nodes per tile frontier
+constexpr int kFrontier = 256;              // nodes per tile frontier
 constexpr uint32_t kBigFlag = 0x80000000u;  // staged object tested pixel-parallel
-constexpr int kSmallArea = 48;            // largest pixel range tested object-parallel
-constexpr double kRangeEps = 1e-7;        // px, widens every pixel range
+constexpr int kSmallArea = 48;              // largest pixel range tested object-parallel
+constexpr double kRangeEps = 1e-7;          // px, widens every pixel range
+constexpr int kCandBytes = 16 + 16 + 8 + 4; // staged object: a, d, 1/|d|^2, range
 
 __device__ inline uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Keeps a tile's workgroups on one XCD: workgroup b is dispatched to XCD
-// b % 8, so consecutive logical ids are dealt out XCD by XCD.
-__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t n) {
-    const uint32_t x = b & 7u, l = b >> 3, per = n >> 3, rem = n & 7u;
-    return x * per + min(x, rem) + l;
-}
-
-__host__ __device__ constexpr int stack_words(int levels) { return 64 * (levels > 0 ? levels : 1); }
+// The frontier level holds at most kFrontier entries, every level below it at
+// most 64 (a level is pushed only when none of its entries remain).
+__host__ __device__ constexpr int stack_words(int levels) { return 64 * (levels > 0 ? levels : 1) + kFrontier; }
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 // LDS of one wavefront: stack | staged objects (SoA) | block mask rows.
-__host__ __device__ inline size_t wave_lds_bytes(int cap, int levels, int seg, int bs) {
-    const size_t per = seg ? (16 + 16 + 8 + 4) : (16 + 4);
-    return align16((size_t)stack_words(levels) * 4) + align16((size_t)cap * per) + align16((size_t)bs * 4);
+__host__ __device__ inline size_t wave_lds_bytes(int cap, int levels, int bs) {
+    return align16((size_t)stack_words(levels) * 4) + align16((size_t)cap * kCandBytes) + align16((size_t)bs * 4);
 }
 
-__global__ __launch_bounds__(256) void k_tile_frontier(DevIndex ix, const DevTile *__restrict__ tiles,
-                                                       int64_t n_tiles, double r, uint32_t *__restrict__ frontier,
-                                                       int32_t *__restrict__ fmeta) {
+__device__ inline bool meets(const double4 &nb, double qx0, double qx1, double qy0, double qy1) {
+    return nb.x <= qx1 && nb.z >= qx0 && nb.y <= qy1 && nb.w >= qy0;
+}
+
+__global__ __launch_bounds__(256) void k_tile_frontier(const DevIndex *__restrict__ ixs,
+                                                       const DevReq *__restrict__ reqs, int64_t n_req,
+                                                       uint32_t *__restrict__ frontier, int32_t *__restrict__ fmeta,
+                                                       int *__restrict__ counter, uint32_t *__restrict__ list,
+                                                       uint8_t *__restrict__ out) {
     __shared__ uint32_t buf[4][2][kFrontier];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps per-tile values scalar
     const int64_t t = (int64_t)blockIdx.x * 4 + wv;
-    if (t >= n_tiles) return;
-    const DevTile tl = tiles[t];
-    const double iS = ldexp(1.0, -8 - tl.z);
-    const double ox = 256.0 * (double)tl.x, oy = 256.0 * (double)tl.y;
-    const double m = r + kCullPad;
+    if (t >= n_req) return;
+    const DevReq rq = reqs[t];
+    const DevIndex ix = ixs[rq.index];
+    const double iS = ldexp(1.0, -8 - rq.z);
+    const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
+    const double m = rq.r + kCullPad;
     const double qx0 = (ox + (0.5 - m)) * iS, qx1 = (ox + (255.5 + m)) * iS;
     const double qy0 = (oy + (0.5 - m)) * iS, qy1 = (oy + (255.5 + m)) * iS;
     uint32_t *cur = buf[wv][0], *nxt = buf[wv][1];
     int ncur = 0, lvl = ix.levels - 1;
-    if (ix.levels > 0) {
-        const double4 rb = ix.nodes[ix.meta[ix.levels - 1]];
-        if (rb.x <= qx1 && rb.z >= qx0 && rb.y <= qy1 && rb.w >= qy0) {
-            if (lane == 0) cur[0] = 0;
-            ncur = 1;
-        }
+    if (ix.levels > 0 && meets(ix.nodes[ix.meta[ix.levels - 1]], qx0, qx1, qy0, qy1)) {
+        if (lane == 0) cur[0] = 0;
+        ncur = 1;
     }
     __builtin_amdgcn_wave_barrier();
     while (lvl > 0 && ncur > 0) {
@@ -89,10 +99,7 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevIndex ix, const DevTil
             int64_t child = 0;
             if (k < ncur * kFan) {
                 child = (int64_t)cur[k / kFan] * kFan + (k % kFan);
-                if (child < cnt) {
-                    const double4 nb = ix.nodes[off + child];
-                    hit = nb.x <= qx1 && nb.z >= qx0 && nb.y <= qy1 && nb.w >= qy0;
-                }
+                hit = child < cnt && meets(ix.nodes[off + child], qx0, qx1, qy0, qy1);
             }
             const uint64_t hm = __ballot(hit);
             const int pos = nn + (int)lanes_below(hm);
@@ -108,49 +115,51 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevIndex ix, const DevTil
         ncur = nn;
         --lvl;
     }
-    if (lane < ncur) frontier[t * kFrontier + lane] = cur[lane];
+    if (ncur == 0) {
+        // no data within r of the tile: the whole mask is zero
+        uint4 *m4 = reinterpret_cast<uint4 *>(out + t * (int64_t)HV_MASK_BYTES);
+        for (int k = lane; k < HV_MASK_BYTES / 16; k += 64) m4[k] = make_uint4(0, 0, 0, 0);
+        return;
+    }
+    for (int k = lane; k < ncur; k += 64) frontier[t * kFrontier + k] = cur[k];
     if (lane == 0) {
         fmeta[2 * t] = ncur;
         fmeta[2 * t + 1] = lvl;
+        list[atomicAdd(counter, 1)] = (uint32_t)t;
     }
 }
 
+struct WaveLds {
+    uint32_t *stk;
+    double2 *ca;     // first point of the staged object (tile-local px)
+    double2 *cd;     // segment direction
+    double *ci;      // 1 / |direction|^2 (0 for a point or a zero-length segment)
+    uint32_t *crng;  // block pixel range | kBigFlag
+    uint32_t *mrow;  // block rows lit object-parallel
+};
+
+// One pixel block of tile t: traversal, staging, tests, mask write.
 template <int BS, int SEG>
-__global__ __launch_bounds__(256) void k_query_tiles(DevIndex ix, const DevTile *__restrict__ tiles,
-                                                     const uint32_t *__restrict__ frontier,
-                                                     const int32_t *__restrict__ fmeta, int64_t n_tiles, double r,
-                                                     uint8_t *__restrict__ out, int cap, int xcd) {
-    extern __shared__ double4 smem[];
+__device__ __forceinline__ void block_query(const DevIndex &ix, const DevReq &rq, int64_t t, int b,
+                                            const uint32_t *__restrict__ frontier,
+                                            const int32_t *__restrict__ fmeta, uint8_t *__restrict__ out,
+                                            int cap, const WaveLds &L, int lane) {
     constexpr int NB = 256 / BS;      // blocks per tile row
-    constexpr int BPT = NB * NB;      // blocks per tile
     constexpr int PPL = BS * BS / 64; // pixels per lane (pixel-parallel layout)
     constexpr int ROWSTEP = 64 / BS;  // rows between a lane's pixels
     constexpr uint32_t FULL = (1u << PPL) - 1u;
+    uint32_t *stk = L.stk;
+    double2 *ca = L.ca;
+    double2 *cd = L.cd;
+    double *ci = L.ci;
+    uint32_t *crng = L.crng;
+    uint32_t *mrow = L.mrow;
 
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    unsigned char *wbase = reinterpret_cast<unsigned char *>(smem) + wv * wave_lds_bytes(cap, ix.levels, SEG, BS);
-    uint32_t *stk = reinterpret_cast<uint32_t *>(wbase);
-    unsigned char *cbase = wbase + align16((size_t)stack_words(ix.levels) * 4);
-    double2 *ca = reinterpret_cast<double2 *>(cbase);              // first point (tile-local px)
-    double2 *cd = ca + cap;                                         // segment direction (segments only)
-    double *ci = reinterpret_cast<double *>(cd + cap);              // 1 / |direction|^2 (segments only)
-    uint32_t *crng = SEG ? reinterpret_cast<uint32_t *>(ci + cap)   // pixel range | big flag
-                         : reinterpret_cast<uint32_t *>(ca + cap);
-    uint32_t *mrow = reinterpret_cast<uint32_t *>(cbase + align16((size_t)cap * (SEG ? 44 : 20)));
-
-    const uint32_t bid = xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int64_t wid = (int64_t)bid * wpb + wv;
-    if (wid >= n_tiles * BPT) return;
-    const int64_t t = wid / BPT;
-    const int b = (int)(wid - t * BPT);
     const int bx = b % NB, by = b / NB;
-    const DevTile tl = tiles[t];
-
-    const double S = ldexp(256.0, tl.z);       // world size in pixels
-    const double iS = ldexp(1.0, -8 - tl.z);   // 1 / S, exact
-    const double ox = 256.0 * (double)tl.x, oy = 256.0 * (double)tl.y;
+    const double r = rq.r;
+    const double S = ldexp(256.0, rq.z);       // world size in pixels
+    const double iS = ldexp(1.0, -8 - rq.z);   // 1 / S, exact
+    const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
     const double i0 = (double)(bx * BS), j0 = (double)(by * BS);
     const double m = r + kCullPad;
     // cull box (normalised): first pixel centre - m .. last pixel centre + m
@@ -170,17 +179,19 @@ __global__ __launch_bounds__(256) void k_query_tiles(DevIndex ix, const DevTile 
     int ncand = 0;
     bool all_lit = false;
     {
+        // the tile's frontier, tested against the block's box in rounds of 64
         const int fcount = fmeta[2 * t], flevel = fmeta[2 * t + 1];
-        bool hit = false;
-        uint32_t node = 0;
-        if (lane < fcount) {
-            node = frontier[t * kFrontier + lane];
-            const double4 nb = ix.nodes[ix.meta[flevel] + node];
-            hit = nb.x <= qx1 && nb.z >= qx0 && nb.y <= qy1 && nb.w >= qy0;
+        for (int base = 0; base < fcount; base += 64) {
+            bool hit = false;
+            uint32_t node = 0;
+            if (base + lane < fcount) {
+                node = frontier[t * kFrontier + base + lane];
+                hit = meets(ix.nodes[ix.meta[flevel] + node], qx0, qx1, qy0, qy1);
+            }
+            const uint64_t hm = __ballot(hit);
+            if (hit) stk[sp + (int)lanes_below(hm)] = ((uint32_t)flevel << kLevelShift) | node;
+            sp += __popcll(hm);
         }
-        const uint64_t hm = __ballot(hit);
-        if (hit) stk[lanes_below(hm)] = ((uint32_t)flevel << kLevelShift) | node;
-        sp = __popcll(hm);
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(256) void k_query_tiles(DevIndex ix, const DevTile 
             if (c < ncand) {
                 const uint32_t rg = crng[c];
                 if (!(rg & kBigFlag)) {
-                    const int ilo = rg & 15, ihi = (rg >> 4) & 15, jlo = (rg >> 8) & 15, jhi = (rg >> 12) & 15;
+                    const int ilo = rg & 31, ihi = (rg >> 5) & 31, jlo = (rg >> 10) & 31, jhi = (rg >> 15) & 31;
                     const double2 a = ca[c];
                     double2 d = make_double2(0.0, 0.0);
                     double inv = 0.0;
@@ -269,13 +280,10 @@ __global__ __launch_bounds__(256) void k_query_tiles(DevIndex ix, const DevTile 
         }
         const int npop = __popcll(__ballot(nv && c == 0));
         if (lvl > 0) {
-            bool hit = false;
             const int cl = lvl - 1;
             const int64_t child = (int64_t)node * kFan + c;
-            if (nv && child < ix.meta[kMaxLevels + cl]) {
-                const double4 nb = ix.nodes[ix.meta[cl] + child];
-                hit = nb.x <= qx1 && nb.z >= qx0 && nb.y <= qy1 && nb.w >= qy0;
-            }
+            const bool hit = nv && child < ix.meta[kMaxLevels + cl] &&
+                             meets(ix.nodes[ix.meta[cl] + child], qx0, qx1, qy0, qy1);
             sp -= npop;
             __builtin_amdgcn_wave_barrier();
             const uint64_t hm = __ballot(hit);
@@ -308,7 +316,7 @@ __global__ __launch_bounds__(256) void k_query_tiles(DevIndex ix, const DevTile 
                     if (flo_i <= fhi_i && flo_j <= fhi_j) {
                         keep = true;
                         const int ilo = (int)flo_i, ihi = (int)fhi_i, jlo = (int)flo_j, jhi = (int)fhi_j;
-                        rg = (uint32_t)ilo | ((uint32_t)ihi << 4) | ((uint32_t)jlo << 8) | ((uint32_t)jhi << 12);
+                        rg = (uint32_t)ilo | ((uint32_t)ihi << 5) | ((uint32_t)jlo << 10) | ((uint32_t)jhi << 15);
                         if ((ihi - ilo + 1) * (jhi - jlo + 1) > kSmallArea) rg |= kBigFlag;
                     }
                 }
@@ -339,62 +347,141 @@ __global__ __launch_bounds__(256) void k_query_tiles(DevIndex ix, const DevTile 
 
     // mask write: row-major, 32 bytes per row, column i = bit (i & 7) of byte i >> 3
     uint8_t *tm = out + t * (int64_t)HV_MASK_BYTES;
-    if (BS == 8) {
-        const uint64_t bal = __ballot(lit & 1u);
-        if (lane < 8) tm[(by * 8 + lane) * 32 + bx] = (uint8_t)((bal >> (8 * lane)) | mrow[lane]);
-    } else {
-        uint64_t bal[PPL];
+    uint64_t bal[PPL];
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) bal[k] = __ballot((lit >> k) & 1u);
-        if (lane < 16) {
-            const int k = lane >> 2, q = lane & 3;
-            uint64_t v = bal[0];
+    for (int k = 0; k < PPL; ++k) bal[k] = __ballot((lit >> k) & 1u);
+    if (lane < BS) {
+        // ballot k holds rows k * ROWSTEP .. k * ROWSTEP + ROWSTEP - 1, BS bits each
+        const int k = lane / ROWSTEP, q = lane % ROWSTEP;
+        uint64_t v = bal[0];
 #pragma unroll
-            for (int kk = 1; kk < PPL; ++kk) v = k == kk ? bal[kk] : v;
-            const uint32_t row = (uint32_t)((v >> (16 * q)) & 0xffffu) | mrow[lane];
-            *reinterpret_cast<uint16_t *>(tm + (by * BS + lane) * 32 + bx * 2) = (uint16_t)row;
-        }
+        for (int kk = 1; kk < PPL; ++kk) v = k == kk ? bal[kk] : v;
+        const uint32_t row = (uint32_t)((v >> (BS * q)) & ((BS == 64 ? 0ull : (1ull << BS)) - 1ull)) | mrow[lane];
+        uint8_t *dst = tm + (by * BS + lane) * 32 + bx * (BS / 8);
+        if (BS == 8) *dst = (uint8_t)row;
+        else if (BS == 16) *reinterpret_cast<uint16_t *>(dst) = (uint16_t)row;
+        else *reinterpret_cast<uint32_t *>(dst) = row;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_query(const DevIndex *__restrict__ ixs, const DevReq *__restrict__ reqs,
+                                               const uint32_t *__restrict__ frontier,
+                                               const int32_t *__restrict__ fmeta, const int *__restrict__ counter,
+                                               const uint32_t *__restrict__ list, uint8_t *__restrict__ out,
+                                               int cap, int max_levels) {
+    extern __shared__ double4 smem[];
+    constexpr int BPT = (256 / BS) * (256 / BS);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps per-block values scalar
+    const int wpb = blockDim.x >> 6;
+    unsigned char *wbase = reinterpret_cast<unsigned char *>(smem) + wv * wave_lds_bytes(cap, max_levels, BS);
+    WaveLds L;
+    L.stk = reinterpret_cast<uint32_t *>(wbase);
+    unsigned char *cbase = wbase + align16((size_t)stack_words(max_levels) * 4);
+    L.ca = reinterpret_cast<double2 *>(cbase);
+    L.cd = L.ca + cap;
+    L.ci = reinterpret_cast<double *>(L.cd + cap);
+    L.crng = reinterpret_cast<uint32_t *>(L.ci + cap);
+    L.mrow = reinterpret_cast<uint32_t *>(cbase + align16((size_t)cap * kCandBytes));
+
+    const int64_t total = (int64_t)gridDim.x * wpb;
+    const int64_t n_items = (int64_t)(*counter) * BPT;
+    for (int64_t k = (int64_t)blockIdx.x * wpb + wv; k < n_items; k += total) {
+        const int64_t t = list[k / BPT];
+        const int b = (int)(k % BPT);
+        const DevReq rq = reqs[t];
+        const DevIndex ix = ixs[rq.index];
+        if (ix.seg) block_query<BS, 1>(ix, rq, t, b, frontier, fmeta, out, cap, L, lane);
+        else block_query<BS, 0>(ix, rq, t, b, frontier, fmeta, out, cap, L, lane);
     }
 }
+
+struct GridKey {
+    int device, block, waves;
+    size_t lds;
+    int grid;
+};
 
 }  // namespace
 
-size_t query_lds_bytes(const LaunchShape &s, int levels, int seg) {
-    return (size_t)s.waves * wave_lds_bytes(s.cand_cap, levels, seg, s.block);
+size_t query_lds_bytes(const LaunchShape &s, int max_levels) {
+    return (size_t)s.waves * wave_lds_bytes(s.cand_cap, max_levels, s.block);
 }
 
-size_t query_scratch_bytes(int64_t n_tiles) {
-    return (size_t)n_tiles * (sizeof(uint32_t) * kFrontier + 2 * sizeof(int32_t));
+Workspace workspace_layout(int64_t n_req, int n_ix) {
+    Workspace w;
+    w.table_off = 0;
+    w.req_off = align256(sizeof(DevIndex) * (size_t)n_ix);
+    w.counter_off = w.req_off + align256(sizeof(DevReq) * (size_t)n_req);
+    w.frontier_off = w.counter_off + 256;
+    w.fmeta_off = w.frontier_off + align256(sizeof(uint32_t) * kFrontier * (size_t)n_req);
+    w.list_off = w.fmeta_off + align256(sizeof(int32_t) * 2 * (size_t)n_req);
+    w.total = w.list_off + align256(sizeof(uint32_t) * (size_t)n_req);
+    return w;
 }
 
-hipError_t launch_query_tiles(const DevIndex &ix, const DevTile *tiles, int64_t n_tiles, double r, uint8_t *out,
-                              const LaunchShape &s, void *scratch, hipStream_t st) {
+void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq *reqs, int64_t n_req,
+                unsigned char *host) {
+    memcpy(host + w.table_off, ixs, sizeof(DevIndex) * (size_t)n_ix);
+    memcpy(host + w.req_off, reqs, sizeof(DevReq) * (size_t)n_req);
+    memset(host + w.counter_off, 0, 256);
+}
+
+int persistent_grid(const LaunchShape &s, int max_levels) {
+    static std::mutex mu;
+    static GridKey cache[16];
+    static int ncache = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    const size_t lds = query_lds_bytes(s, max_levels);
+    std::lock_guard<std::mutex> g(mu);
+    for (int k = 0; k < ncache; ++k)
+        if (cache[k].device == dev && cache[k].block == s.block && cache[k].waves == s.waves && cache[k].lds == lds)
+            return cache[k].grid;
+    int per_cu = 0, cus = 0;
+    hipError_t e = s.block == 8    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<8>, 64 * s.waves, lds)
+                   : s.block == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<16>, 64 * s.waves, lds)
+                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<32>, 64 * s.waves, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    (void)hipGetLastError();
+    // ten times what fits at once: the dispatcher then hands out the
+    // remaining workgroups as others finish, which evens out uneven blocks
+    const int grid = 10 * per_cu * cus;
+    if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, lds, grid};
+    return grid;
+}
+
+hipError_t launch_query(const Workspace &w, unsigned char *dws, int64_t n_req, int max_levels, uint8_t *out,
+                        const LaunchShape &s, hipStream_t st) {
+    if (n_req == 0) return hipSuccess;
+    const DevIndex *ixs = reinterpret_cast<const DevIndex *>(dws + w.table_off);
+    const DevReq *reqs = reinterpret_cast<const DevReq *>(dws + w.req_off);
+    int *counter = reinterpret_cast<int *>(dws + w.counter_off);
+    uint32_t *frontier = reinterpret_cast<uint32_t *>(dws + w.frontier_off);
+    int32_t *fmeta = reinterpret_cast<int32_t *>(dws + w.fmeta_off);
+    uint32_t *list = reinterpret_cast<uint32_t *>(dws + w.list_off);
+    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, ixs, reqs, n_req,
+                       frontier, fmeta, counter, list, out);
+    const size_t lds = query_lds_bytes(s, max_levels);
+    // never more workgroups than there are blocks to render
     const int64_t bpt = (256 / s.block) * (256 / s.block);
-    const size_t lds = query_lds_bytes(s, ix.levels, ix.seg);
-    const dim3 b((uint32_t)(64 * s.waves));
-    uint32_t *frontier = reinterpret_cast<uint32_t *>(scratch);
-    int32_t *fmeta = reinterpret_cast<int32_t *>(frontier + n_tiles * kFrontier);
-    // at most 2^20 tiles per launch keeps the grid far below 2^31 workgroups
-    constexpr int64_t kChunk = int64_t(1) << 20;
-    for (int64_t off = 0; off < n_tiles; off += kChunk) {
-        const int64_t nt = n_tiles - off < kChunk ? n_tiles - off : kChunk;
-        const DevTile *tp = tiles + off;
-        uint32_t *fp = frontier + off * kFrontier;
-        int32_t *mp = fmeta + 2 * off;
-        uint8_t *op = out + off * (int64_t)HV_MASK_BYTES;
-        hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((nt + 3) / 4)), dim3(256), 0, st, ix, tp, nt, r, fp, mp);
-        const dim3 g((uint32_t)((nt * bpt + s.waves - 1) / s.waves));
-        if (s.block == 8) {
-            if (ix.seg) hipLaunchKernelGGL((k_query_tiles<8, 1>), g, b, lds, st, ix, tp, fp, mp, nt, r, op, s.cand_cap, s.xcd_remap);
-            else hipLaunchKernelGGL((k_query_tiles<8, 0>), g, b, lds, st, ix, tp, fp, mp, nt, r, op, s.cand_cap, s.xcd_remap);
-        } else {
-            if (ix.seg) hipLaunchKernelGGL((k_query_tiles<16, 1>), g, b, lds, st, ix, tp, fp, mp, nt, r, op, s.cand_cap, s.xcd_remap);
-            else hipLaunchKernelGGL((k_query_tiles<16, 0>), g, b, lds, st, ix, tp, fp, mp, nt, r, op, s.cand_cap, s.xcd_remap);
-        }
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int64_t need = (n_req * bpt + s.waves - 1) / s.waves;
+    int64_t grid = s.grid > 0 ? s.grid : persistent_grid(s, max_levels);
+    if (grid > need) grid = need;
+    const dim3 g((uint32_t)grid), b((uint32_t)(64 * s.waves));
+    if (s.block == 8)
+        hipLaunchKernelGGL(k_query<8>, g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out, s.cand_cap,
+                           max_levels);
+    else if (s.block == 16)
+        hipLaunchKernelGGL(k_query<16>, g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out, s.cand_cap,
+                           max_levels);
+    else
+        hipLaunchKernelGGL(k_query<32>, g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out, s.cand_cap,
+                           max_levels);
+    return hipGetLastError();
 }
 
 }  // namespace hv

@@ -99,15 +99,16 @@ def test_deterministic_and_permutation_invariant(hv, torch):
         hv.hv_free(h)
 
 
-SHAPES = [dict(block=b, cand_cap=c, waves_per_wg=w, xcd_remap=x)
-          for b in (8, 16) for c in (64, 128, 512) for w in (1, 2, 4) for x in (0, 1)
+SHAPES = [dict(block=b, cand_cap=c, waves_per_wg=w, grid_wgs=g)
+          for b in (8, 16, 32) for c in (64, 128, 512) for w in (1, 2, 4) for g in (0, 7)
           if not (c == 512 and w == 4)]
 
 
 def test_launch_shapes_identical(hv, torch):
     """Every launch shape (block size, LDS candidate capacity -- 64 forces a
-    flush after every leaf step --, waves per workgroup, XCD remap) gives
-    bit-identical masks."""
+    flush after every leaf step --, waves per workgroup, persistent grid
+    size, including a 7-workgroup grid that makes each wave loop over many
+    blocks) gives bit-identical masks."""
     segs = hvgen.gen_c2_segments(seed=8, n_segments=400_000)
     pts = hvgen.gen_c3_points(300_000)
     rng = np.random.default_rng(9)
