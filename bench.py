@@ -81,7 +81,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-tile", action="store_true")
     ap.add_argument("--launch", default="", help="JSON hv_launch fields, e.g. '{\"block\": 8}'")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes per step (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        a = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup + args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "steps": args.warmup + args.steps}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU design is described but not built", file=sys.stderr)

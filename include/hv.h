@@ -113,19 +113,29 @@ const char *hv_last_error(void);
 /* Set the calling thread's stream (a hipStream_t; NULL = null stream). */
 int hv_set_stream(void *hip_stream);
 
-/* Launch shape of the query kernel; zero fields take the defaults. */
+/* Launch shape of the query kernel.  hv_render_tiles uses region = 32 with
+ * one wavefront per workgroup; through hv_render_tiles_ex, zero fields take
+ * block 16, cand_cap 64, waves_per_wg 2 (1 in region mode) and a grid that
+ * fills the GPU, and region = 0 selects one wavefront per pixel block. */
 typedef struct {
     int32_t block;          /* pixel block per wavefront: 8, 16 or 32 (1, 4 or 16 px/lane) */
     int32_t cand_cap;       /* LDS candidate capacity per wavefront, >= 64 */
     int32_t waves_per_wg;   /* wavefronts per workgroup: 1, 2 or 4 */
     int32_t grid_wgs;       /* workgroups of the persistent query kernel; 0 = as many as fit on the GPU */
+    int32_t region;         /* 0: one wavefront per pixel block; 32 or 64: one workgroup per region of
+                               that side whose queued objects are dealt out over all lanes (block is
+                               then unused and cand_cap sizes the queue) */
+    int32_t objs_per_lane;  /* region mode: objects each lane loads per leaf step, 1, 2 or 4;
+                               cand_cap must be >= 64 * waves_per_wg * objs_per_lane */
 } hv_launch;
 
 /* hv_render_tiles with an explicit launch shape (autotuning and variant
  * tests).  Every valid shape produces identical masks.  Extra HV_EINVAL
  * cases: block not 8, 16 or 32, cand_cap < 64 or > 4096, waves_per_wg not 1,
- * 2 or 4, grid_wgs outside [0, 2^20], or a shape needing more than 64 KiB
- * of LDS per workgroup. */
+ * 2 or 4, grid_wgs outside [0, 2^20], region not 0, 32 or 64,
+ * objs_per_lane not 1, 2 or 4, cand_cap below 64 * waves_per_wg *
+ * objs_per_lane in region mode, or a shape needing more than 64 KiB of LDS
+ * per workgroup. */
 int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
                        const hv_style *style, uint8_t *out_masks, const hv_launch *launch);
 

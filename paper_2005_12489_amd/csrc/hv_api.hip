@@ -78,16 +78,27 @@ int validate_style(const hv_style *style) {
 }
 
 int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s) {
+    // default: one single-wave workgroup per 32x32 region (fastest on the
+    // benchmark workload); hv_launch selects any other shape
     s->block = 16;
     s->cand_cap = 64;
-    s->waves = 2;
+    s->waves = 1;
     s->grid = 0;
+    s->region = 32;
+    s->opl = 1;
     if (l) {
-        if (l->block) s->block = l->block;
-        if (l->cand_cap) s->cand_cap = l->cand_cap;
-        if (l->waves_per_wg) s->waves = l->waves_per_wg;
+        s->block = l->block ? l->block : 16;
+        s->cand_cap = l->cand_cap ? l->cand_cap : 64;
+        s->waves = l->waves_per_wg ? l->waves_per_wg : (l->region ? 1 : 2);
         s->grid = l->grid_wgs;
+        s->region = l->region;
+        s->opl = l->objs_per_lane ? l->objs_per_lane : 1;
     }
+    if (s->opl != 1 && s->opl != 2 && s->opl != 4) return fail(HV_EINVAL, "launch.objs_per_lane must be 1, 2 or 4");
+    if (s->region != 0 && s->region != 32 && s->region != 64)
+        return fail(HV_EINVAL, "launch.region must be 0, 32 or 64");
+    if (s->region && s->cand_cap < 64 * s->waves * s->opl)
+        return fail(HV_EINVAL, "launch.cand_cap must be at least 64 * waves_per_wg * objs_per_lane in region mode");
     if (s->block != 8 && s->block != 16 && s->block != 32)
         return fail(HV_EINVAL, "launch.block must be 8, 16 or 32");
     if (s->cand_cap < 64 || s->cand_cap > 4096) return fail(HV_EINVAL, "launch.cand_cap must be in [64, 4096]");

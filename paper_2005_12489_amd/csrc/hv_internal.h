@@ -65,6 +65,8 @@ struct LaunchShape {
     int cand_cap;     // staged candidates per wave
     int waves;        // waves per workgroup
     int grid;         // workgroups of the persistent query kernel (0: fill the GPU)
+    int region;       // 0: one wave per block; 32 or 64: one workgroup per region of that side
+    int opl;          // region mode: objects loaded per lane at a leaf step (1, 2 or 4)
 };
 
 // LDS bytes per workgroup for a shape and the deepest index of a batch.

@@ -138,6 +138,37 @@ struct WaveLds {
     uint32_t *mrow;  // block rows lit object-parallel
 };
 
+// Work items are (position in the compacted tile list, part of the tile).
+// Workgroup b runs on XCD b % 8; dealing list positions to XCDs the same way
+// keeps all parts of a tile on one XCD, so the partial cache lines its mask
+// rows are written in merge in that XCD's L2 before they reach HBM.
+struct ItemMap {
+    int64_t first, step, n;  // local items first, first + step, ... < n
+    int x;                   // XCD slot (-1: no dealing)
+    __device__ inline ItemMap(int64_t count, int per_tile) {
+        const int64_t g = gridDim.x, b = blockIdx.x;
+        // small batches keep every XCD busy instead (a lone tile would
+        // otherwise land on one XCD)
+        if (g >= 8 && count >= 32) {
+            x = (int)(b & 7);
+            const int64_t gx = g / 8 + ((b & 7) < (g & 7) ? 1 : 0);
+            first = b >> 3;
+            step = gx;
+            const int64_t tiles_x = count > x ? (count - x + 7) / 8 : 0;
+            n = tiles_x * per_tile;
+        } else {
+            x = -1;
+            first = b;
+            step = g;
+            n = count * per_tile;
+        }
+    }
+    // list position and part of local item u
+    __device__ inline int64_t pos(int64_t u, int per_tile) const {
+        return x < 0 ? u / per_tile : x + 8 * (u / per_tile);
+    }
+};
+
 // One pixel block of tile t: traversal, staging, tests, mask write.
 template <int BS, int SEG>
 __device__ __forceinline__ void block_query(const DevIndex &ix, const DevReq &rq, int64_t t, int b,
@@ -386,11 +417,13 @@ __global__ __launch_bounds__(256) void k_query(const DevIndex *__restrict__ ixs,
     L.crng = reinterpret_cast<uint32_t *>(L.ci + cap);
     L.mrow = reinterpret_cast<uint32_t *>(cbase + align16((size_t)cap * kCandBytes));
 
-    const int64_t total = (int64_t)gridDim.x * wpb;
-    const int64_t n_items = (int64_t)(*counter) * BPT;
-    for (int64_t k = (int64_t)blockIdx.x * wpb + wv; k < n_items; k += total) {
-        const int64_t t = list[k / BPT];
-        const int b = (int)(k % BPT);
+    // a workgroup's waves take consecutive blocks of one tile
+    const int per_wg = (BPT + wpb - 1) / wpb;
+    const ItemMap im(*counter, per_wg);
+    for (int64_t u = im.first; u < im.n; u += im.step) {
+        const int b = (int)(u % per_wg) * wpb + wv;
+        if (b >= BPT) continue;
+        const int64_t t = list[im.pos(u, per_wg)];
         const DevReq rq = reqs[t];
         const DevIndex ix = ixs[rq.index];
         if (ix.seg) block_query<BS, 1>(ix, rq, t, b, frontier, fmeta, out, cap, L, lane);
@@ -398,8 +431,323 @@ __global__ __launch_bounds__(256) void k_query(const DevIndex *__restrict__ ixs,
     }
 }
 
+// ------------------------------------------------------------ region mode
+// One workgroup per RS x RS region of a tile.  It walks the tree once with
+// the region's box grown by r, all lanes testing children together, and
+// queues every object that meets the box in LDS with the range of region
+// pixels within r of the object's box (the per-pixel box filter of
+// Algorithm 1 seen from the object's side).  The queue is then dealt out as
+// work cells -- (object, pixel row, group of 8 columns) -- evenly over all
+// lanes, whatever the objects' sizes: each cell tests at most 8 pixels
+// with the exact FP64 distance and sets the lit ones with one LDS OR.
+
+__host__ __device__ inline int region_stack_words(int levels, int threads) {
+    return kFrontier + threads * (levels > 0 ? levels : 1);
+}
+
+// stack | queued objects (SoA) | cell prefix sums | mask rows | control | scan scratch
+__host__ __device__ inline size_t region_lds_bytes(int cap, int levels, int threads, int rs) {
+    return align16((size_t)region_stack_words(levels, threads) * 4) + align16((size_t)cap * kCandBytes) +
+           align16((size_t)(cap + 1) * 4) + align16((size_t)rs * (rs / 32) * 4) + 16 + 64;
+}
+
+struct RegionLds {
+    uint32_t *stk;
+    double2 *ca, *cd;
+    double *ci;
+    uint32_t *crng;  // ilo | ihi << 6 | jlo << 12 | jhi << 18 (region pixels)
+    uint32_t *cpre;  // exclusive prefix sums of work cells per queued object
+    uint32_t *mask;  // RS rows x RS/32 words
+    int *ctl;        // [0] stack size, [1] queued objects
+    uint32_t *scan;  // 16 words
+};
+
+// Reserves popcount(hm) consecutive slots of *counter for the wave's set lanes.
+__device__ inline int wave_alloc(int *counter, uint64_t hm, int lane) {
+    int base = 0;
+    if (hm) {
+        const int first = __ffsll((unsigned long long)hm) - 1;
+        if (lane == first) base = atomicAdd(counter, __popcll(hm));
+        base = __shfl(base, first, 64);
+    }
+    return base + (int)lanes_below(hm);
+}
+
+// Exclusive scan over the workgroup (blockDim a multiple of 64, at most
+// 1024); `scan` holds 16 words of LDS.  Every thread must call it.
+__device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *total, uint32_t *scan) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) scan[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        const uint32_t sk = scan[k];
+        if (k < w) off += sk;
+        tot += sk;
+    }
+    *total = tot;
+    __syncthreads();
+    return off + x - v;
+}
+
+__device__ inline int region_cells(uint32_t rg) {
+    const int ilo = rg & 63, ihi = (rg >> 6) & 63, jlo = (rg >> 12) & 63, jhi = (rg >> 18) & 63;
+    return (jhi - jlo + 1) * ((ihi >> 3) - (ilo >> 3) + 1);
+}
+
+template <int RS, int SEG, int OPL>
+__device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &rq, int64_t t, int reg,
+                                             const uint32_t *__restrict__ frontier,
+                                             const int32_t *__restrict__ fmeta, uint8_t *__restrict__ out,
+                                             int cap, const RegionLds &L) {
+    constexpr int NR = 256 / RS;
+    constexpr int W = RS / 32;  // mask words per region row
+    const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
+    uint32_t *stk = L.stk;
+    uint32_t *mask = L.mask;
+    int *ctl = L.ctl;
+
+    const int rx = reg % NR, ry = reg / NR;
+    const double r = rq.r, r2 = r * r;
+    const double S = ldexp(256.0, rq.z);
+    const double iS = ldexp(1.0, -8 - rq.z);
+    const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
+    const double i0 = (double)(rx * RS), j0 = (double)(ry * RS);
+    const double m = r + kCullPad;
+    const double qx0 = ((ox + i0) + (0.5 - m)) * iS;
+    const double qx1 = ((ox + i0) + ((RS - 0.5) + m)) * iS;
+    const double qy0 = ((oy + j0) + (0.5 - m)) * iS;
+    const double qy1 = ((oy + j0) + ((RS - 0.5) + m)) * iS;
+
+    for (int k = tid; k < RS * W; k += nthr) mask[k] = 0;
+    if (tid == 0) {
+        ctl[0] = 0;
+        ctl[1] = 0;
+    }
+    __syncthreads();
+    {
+        const int fcount = fmeta[2 * t], flevel = fmeta[2 * t + 1];
+        for (int base = 0; base < fcount; base += nthr) {
+            bool hit = false;
+            uint32_t node = 0;
+            if (base + tid < fcount) {
+                node = frontier[t * kFrontier + base + tid];
+                hit = meets(ix.nodes[ix.meta[flevel] + node], qx0, qx1, qy0, qy1);
+            }
+            const int pos = wave_alloc(&ctl[0], __ballot(hit), lane);
+            if (hit) stk[pos] = ((uint32_t)flevel << kLevelShift) | node;
+        }
+    }
+    __syncthreads();
+
+    // Tests every queued object against its pixels; returns true once the
+    // whole region is lit.
+    auto drain = [&]() -> bool {
+        const int nq = ctl[1];
+        const int per = (nq + nthr - 1) / nthr;
+        const int q0 = min(nq, tid * per), q1 = min(nq, q0 + per);
+        uint32_t cnt = 0;
+        for (int q = q0; q < q1; ++q) cnt += (uint32_t)region_cells(L.crng[q]);
+        uint32_t tot;
+        uint32_t off = wg_excl_scan(cnt, &tot, L.scan);
+        for (int q = q0; q < q1; ++q) {
+            L.cpre[q] = off;
+            off += (uint32_t)region_cells(L.crng[q]);
+        }
+        __syncthreads();
+        for (uint32_t cell = tid; cell < tot; cell += nthr) {
+            int lo = 0, hi = nq - 1;  // last object whose first cell is <= cell
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.cpre[mid] <= cell) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t rg = L.crng[lo];
+            const int ilo = rg & 63, ihi = (rg >> 6) & 63, jlo = (rg >> 12) & 63;
+            const int g0 = ilo >> 3, ng = (ihi >> 3) - g0 + 1;
+            const int local = (int)(cell - L.cpre[lo]);
+            // local / ng by reciprocal: exact here (local < 2^10, ng <= 9)
+            const int dq = (int)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)ng));
+            const int row = jlo + dq, g = g0 + (local - dq * ng);
+            if (row >= RS || g < g0 || g >= g0 + ng) continue;  // never taken: the quotient is exact
+            const int c0 = max(ilo, 8 * g), c1 = min(ihi, 8 * g + 7);
+            const double2 a = L.ca[lo];
+            double2 d = make_double2(0.0, 0.0);
+            double inv = 0.0;
+            if (SEG) {
+                d = L.cd[lo];
+                inv = L.ci[lo];
+            }
+            const double wy = (j0 + (double)row + 0.5) - a.y;
+            uint32_t bits = 0;
+            for (int ii = c0; ii <= c1; ++ii) {
+                const double wx = (i0 + (double)ii + 0.5) - a.x;
+                double d2;
+                if (SEG) {
+                    double tt = (wx * d.x + wy * d.y) * inv;
+                    tt = fmin(fmax(tt, 0.0), 1.0);
+                    const double ex = wx - tt * d.x, ey = wy - tt * d.y;
+                    d2 = ex * ex + ey * ey;
+                } else {
+                    d2 = wx * wx + wy * wy;
+                }
+                if (d2 <= r2) bits |= 1u << (ii & 31);
+            }
+            if (bits) atomicOr(&mask[row * W + (c0 >> 5)], bits);
+        }
+        __syncthreads();
+        bool full = true;
+        for (int k = tid; k < RS * W; k += nthr) full &= mask[k] == 0xffffffffu;
+        const bool all = __syncthreads_and(full);
+        if (tid == 0) ctl[1] = 0;
+        __syncthreads();
+        return all;
+    };
+
+    bool done = false;
+    for (;;) {
+        const int sp = ctl[0];
+        if (sp == 0) break;
+        const int lvl = (int)(stk[sp - 1] >> kLevelShift);
+        // an inner step tests one child per thread; a leaf step OPL objects per thread
+        const int per_step = lvl > 0 ? nthr / kFan : nthr * OPL / kLeaf;
+        const bool top = tid < per_step && tid < sp && (int)(stk[sp - 1 - tid] >> kLevelShift) == lvl;
+        const int npop = __syncthreads_count(top);
+        if (lvl > 0) {
+            const int j = tid >> 4, c = tid & 15;  // popped node, child of it
+            const uint32_t node = j < npop ? (stk[sp - 1 - j] & kIdxMask) : 0u;
+            if (tid == 0) ctl[0] = sp - npop;
+            __syncthreads();
+            const int cl = lvl - 1;
+            const int64_t child = (int64_t)node * kFan + c;
+            const bool hit = j < npop && child < ix.meta[kMaxLevels + cl] &&
+                             meets(ix.nodes[ix.meta[cl] + child], qx0, qx1, qy0, qy1);
+            const int pos = wave_alloc(&ctl[0], __ballot(hit), lane);
+            if (hit) stk[pos] = ((uint32_t)cl << kLevelShift) | (uint32_t)child;
+        } else {
+            // issue all OPL loads first so that they are in flight together
+            double4 ob[OPL];
+            bool have[OPL];
+#pragma unroll
+            for (int k = 0; k < OPL; ++k) {
+                const int q = k * nthr + tid, j = q >> 4, c = q & 15;
+                have[k] = false;
+                ob[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+                if (j < npop) {
+                    const int64_t o = (int64_t)(stk[sp - 1 - j] & kIdxMask) * kLeaf + c;
+                    if (o < ix.n) {
+                        have[k] = true;
+                        if (SEG) {
+                            ob[k] = reinterpret_cast<const double4 *>(ix.obj)[o];
+                        } else {
+                            const double2 p = reinterpret_cast<const double2 *>(ix.obj)[o];
+                            ob[k] = make_double4(p.x, p.y, p.x, p.y);
+                        }
+                    }
+                }
+            }
+            if (tid == 0) ctl[0] = sp - npop;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < OPL; ++k) {
+                const double ax = ob[k].x, ay = ob[k].y, bxx = ob[k].z, byy = ob[k].w;
+                bool keep = false;
+                double ua = 0, va = 0, ub = 0, vb = 0;
+                uint32_t rg = 0;
+                if (have[k] && fmin(ax, bxx) <= qx1 && fmax(ax, bxx) >= qx0 && fmin(ay, byy) <= qy1 &&
+                    fmax(ay, byy) >= qy0) {
+                    // tile-local pixel frame; scaling by S is exact
+                    ua = ax * S - ox; va = ay * S - oy;
+                    ub = bxx * S - ox; vb = byy * S - oy;
+                    // region pixels whose centre lies within r of the object's box
+                    const double flo_i = fmax(ceil(fmin(ua, ub) - r - 0.5 - i0 - kRangeEps), 0.0);
+                    const double fhi_i = fmin(floor(fmax(ua, ub) + r - 0.5 - i0 + kRangeEps), RS - 1.0);
+                    const double flo_j = fmax(ceil(fmin(va, vb) - r - 0.5 - j0 - kRangeEps), 0.0);
+                    const double fhi_j = fmin(floor(fmax(va, vb) + r - 0.5 - j0 + kRangeEps), RS - 1.0);
+                    if (flo_i <= fhi_i && flo_j <= fhi_j) {
+                        keep = true;
+                        rg = (uint32_t)flo_i | ((uint32_t)fhi_i << 6) | ((uint32_t)flo_j << 12) |
+                             ((uint32_t)fhi_j << 18);
+                    }
+                }
+                const int slot = wave_alloc(&ctl[1], __ballot(keep), lane);
+                if (keep) {
+                    L.ca[slot] = make_double2(ua, va);
+                    if (SEG) {
+                        const double dx = ub - ua, dy = vb - va;
+                        const double l2 = dx * dx + dy * dy;
+                        L.cd[slot] = make_double2(dx, dy);
+                        L.ci[slot] = l2 > 0.0 ? 1.0 / l2 : 0.0;
+                    }
+                    L.crng[slot] = rg;
+                }
+            }
+        }
+        __syncthreads();
+        if (ctl[1] > cap - nthr * OPL && drain()) {
+            done = true;
+            break;
+        }
+    }
+    if (!done && ctl[1] > 0) drain();
+    __syncthreads();
+    uint8_t *tm = out + t * (int64_t)HV_MASK_BYTES;
+    for (int k = tid; k < RS * W; k += nthr) {
+        const int row = k / W, wd = k % W;
+        *reinterpret_cast<uint32_t *>(tm + (ry * RS + row) * 32 + rx * (RS / 8) + 4 * wd) = mask[k];
+    }
+    __syncthreads();
+}
+
+template <int RS, int OPL>
+__global__ __launch_bounds__(256) void k_query_region(const DevIndex *__restrict__ ixs,
+                                                      const DevReq *__restrict__ reqs,
+                                                      const uint32_t *__restrict__ frontier,
+                                                      const int32_t *__restrict__ fmeta,
+                                                      const int *__restrict__ counter,
+                                                      const uint32_t *__restrict__ list, uint8_t *__restrict__ out,
+                                                      int cap, int max_levels) {
+    extern __shared__ double4 smem[];
+    constexpr int RPT = (256 / RS) * (256 / RS);
+    unsigned char *base = reinterpret_cast<unsigned char *>(smem);
+    RegionLds L;
+    L.stk = reinterpret_cast<uint32_t *>(base);
+    unsigned char *cb = base + align16((size_t)region_stack_words(max_levels, blockDim.x) * 4);
+    L.ca = reinterpret_cast<double2 *>(cb);
+    L.cd = L.ca + cap;
+    L.ci = reinterpret_cast<double *>(L.cd + cap);
+    L.crng = reinterpret_cast<uint32_t *>(L.ci + cap);
+    L.cpre = reinterpret_cast<uint32_t *>(cb + align16((size_t)cap * kCandBytes));
+    L.mask = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.cpre) + align16((size_t)(cap + 1) * 4));
+    L.ctl = reinterpret_cast<int *>(L.mask + RS * (RS / 32));
+    L.scan = reinterpret_cast<uint32_t *>(L.ctl + 4);
+    const ItemMap im(*counter, RPT);
+    for (int64_t u = im.first; u < im.n; u += im.step) {
+        const int64_t t = list[im.pos(u, RPT)];
+        const int reg = (int)(u % RPT);
+        const DevReq rq = reqs[t];
+        const DevIndex ix = ixs[rq.index];
+        if (ix.seg) region_query<RS, 1, OPL>(ix, rq, t, reg, frontier, fmeta, out, cap, L);
+        else region_query<RS, 0, OPL>(ix, rq, t, reg, frontier, fmeta, out, cap, L);
+    }
+}
+
+using RegionKernel = void (*)(const DevIndex *, const DevReq *, const uint32_t *, const int32_t *, const int *,
+                             const uint32_t *, uint8_t *, int, int);
+
+RegionKernel region_kernel(const LaunchShape &s) {
+    if (s.region == 32) return s.opl == 4 ? k_query_region<32, 4> : s.opl == 2 ? k_query_region<32, 2> : k_query_region<32, 1>;
+    return s.opl == 4 ? k_query_region<64, 4> : s.opl == 2 ? k_query_region<64, 2> : k_query_region<64, 1>;
+}
+
 struct GridKey {
-    int device, block, waves;
+    int device, block, waves, region, opl;
     size_t lds;
     int grid;
 };
@@ -407,6 +755,7 @@ struct GridKey {
 }  // namespace
 
 size_t query_lds_bytes(const LaunchShape &s, int max_levels) {
+    if (s.region) return region_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region);
     return (size_t)s.waves * wave_lds_bytes(s.cand_cap, max_levels, s.block);
 }
 
@@ -438,19 +787,23 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
     const size_t lds = query_lds_bytes(s, max_levels);
     std::lock_guard<std::mutex> g(mu);
     for (int k = 0; k < ncache; ++k)
-        if (cache[k].device == dev && cache[k].block == s.block && cache[k].waves == s.waves && cache[k].lds == lds)
+        if (cache[k].device == dev && cache[k].block == s.block && cache[k].waves == s.waves &&
+            cache[k].region == s.region && cache[k].opl == s.opl && cache[k].lds == lds)
             return cache[k].grid;
     int per_cu = 0, cus = 0;
-    hipError_t e = s.block == 8    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<8>, 64 * s.waves, lds)
-                   : s.block == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<16>, 64 * s.waves, lds)
-                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<32>, 64 * s.waves, lds);
+    const int thr = 64 * s.waves;
+    hipError_t e;
+    if (s.region) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, region_kernel(s), thr, lds);
+    else if (s.block == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<8>, thr, lds);
+    else if (s.block == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<16>, thr, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<32>, thr, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     (void)hipGetLastError();
     // ten times what fits at once: the dispatcher then hands out the
     // remaining workgroups as others finish, which evens out uneven blocks
     const int grid = 10 * per_cu * cus;
-    if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, lds, grid};
+    if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, s.region, s.opl, lds, grid};
     return grid;
 }
 
@@ -466,13 +819,18 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int64_t n_req, i
     hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, ixs, reqs, n_req,
                        frontier, fmeta, counter, list, out);
     const size_t lds = query_lds_bytes(s, max_levels);
-    // never more workgroups than there are blocks to render
-    const int64_t bpt = (256 / s.block) * (256 / s.block);
-    const int64_t need = (n_req * bpt + s.waves - 1) / s.waves;
+    // never more workgroups than there are blocks (or regions) to render
+    const int64_t per_tile = s.region ? (256 / s.region) * (256 / s.region)
+                                      : ((256 / s.block) * (256 / s.block) + s.waves - 1) / s.waves;
+    // (the item count per XCD is rounded up to whole tiles)
+    const int64_t need = n_req * per_tile;
     int64_t grid = s.grid > 0 ? s.grid : persistent_grid(s, max_levels);
     if (grid > need) grid = need;
     const dim3 g((uint32_t)grid), b((uint32_t)(64 * s.waves));
-    if (s.block == 8)
+    if (s.region)
+        hipLaunchKernelGGL(region_kernel(s), g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out,
+                           s.cand_cap, max_levels);
+    else if (s.block == 8)
         hipLaunchKernelGGL(k_query<8>, g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out, s.cand_cap,
                            max_levels);
     else if (s.block == 16)

@@ -102,6 +102,10 @@ def test_deterministic_and_permutation_invariant(hv, torch):
 SHAPES = [dict(block=b, cand_cap=c, waves_per_wg=w, grid_wgs=g)
           for b in (8, 16, 32) for c in (64, 128, 512) for w in (1, 2, 4) for g in (0, 7)
           if not (c == 512 and w == 4)]
+SHAPES += [dict(region=rs, cand_cap=64 * w * o, waves_per_wg=w, objs_per_lane=o)
+           for rs in (32, 64) for w in (1, 2, 4) for o in (1, 2, 4)]
+SHAPES += [dict(region=rs, cand_cap=512, waves_per_wg=w, objs_per_lane=o, grid_wgs=7)
+           for rs in (32, 64) for w, o in ((1, 1), (2, 4))]
 
 
 def test_launch_shapes_identical(hv, torch):
@@ -111,9 +115,15 @@ def test_launch_shapes_identical(hv, torch):
     blocks) gives bit-identical masks."""
     segs = hvgen.gen_c2_segments(seed=8, n_segments=400_000)
     pts = hvgen.gen_c3_points(300_000)
+    edges = hvgen.gen_c4_edges(seed=12, min_edges=60_000, batch_polygons=2000)
     rng = np.random.default_rng(9)
-    for objs, kind, tiles, r in ((segs, hv.HV_SEGMENTS, hvgen.all_tiles(4), 1.5),
-                                 (pts, hv.HV_POINTS, np.concatenate([hvgen.all_tiles(3), hvgen.all_tiles(7)[rng.integers(0, 16384, 64)]]), 2.0)):
+    t12, _ = hvgen.c4_requests(edges, n=24, seed=13, zlo=11, zhi=14)
+    cases = ((segs, hv.HV_SEGMENTS, hvgen.all_tiles(4), 1.5),
+             (pts, hv.HV_POINTS, np.concatenate([hvgen.all_tiles(3), hvgen.all_tiles(7)[rng.integers(0, 16384, 64)]]), 2.0),
+             # large pixel ranges: wide points and long edges at high zoom
+             (pts[:20000], hv.HV_POINTS, hvgen.all_tiles(3), 40.0),
+             (edges, hv.HV_POLYGON_EDGES, t12, 2.5))
+    for objs, kind, tiles, r in cases:
         h = build(hv, torch, objs, kind)
         ref = None
         for s in SHAPES:
