@@ -166,6 +166,65 @@ int hv_index_info(const hv_index *index, hv_info *info);
 enum { HV_READ_ORDER = 0, HV_READ_OBJECTS = 1, HV_READ_NODES = 2 };
 int hv_index_read(const hv_index *index, int what, int level, void *host_dst, int64_t bytes);
 
+/* ------------------------------------------------------------------ batches
+ * Many heterogeneous requests -- tiles of different indexes, zooms and
+ * styles -- rendered by one launch of the query, the way the paper's engine
+ * hands queued tile tasks to whichever process is idle (Sec. 4.2, 4.3). */
+
+/* One request: a tile of `index` with its own radius / half-width. */
+typedef struct {
+    const hv_index *index;
+    int32_t z, x, y, pad;
+    double r_px;
+} hv_request;
+
+/* Render n requests in one launch.  reqs: host array (copied during the
+ * call); out_masks: device, n * 8192 bytes, 16-byte aligned, request k at
+ * k * 8192.  launch: NULL takes the autotuned shape for the batch's class
+ * (see hv_autotune) or the default.  Every index must live on the current
+ * device.  Errors as hv_render_tiles_ex, plus HV_EINVAL for a NULL index in
+ * a request. */
+int hv_render_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch);
+
+/* A reusable batch executor.  It owns, twice over, a device workspace for
+ * up to max_requests requests over up to max_indexes distinct indexes of at
+ * most max_levels tree levels, and a pinned host staging buffer; for each
+ * it captures one HIP graph [copy staged requests -> frontier kernel ->
+ * query kernel] at creation, so a run is one graph launch.  Runs use the
+ * two slots in turn; a run waits (on the host) until the run that last used
+ * its slot has finished.  launch: the query shape baked into the graphs
+ * (NULL = default).  Returns NULL on error (hv_last_error). */
+typedef struct hv_batcher hv_batcher;
+hv_batcher *hv_batcher_create(int64_t max_requests, int32_t max_indexes, int32_t max_levels,
+                              const hv_launch *launch);
+
+/* Launch one batch on the calling thread's stream (asynchronous).  Same
+ * arguments and errors as hv_render_batch, plus HV_EINVAL when n exceeds
+ * max_requests, the batch names more than max_indexes indexes, or an index
+ * is deeper than max_levels. */
+int hv_batcher_run(hv_batcher *b, const hv_request *reqs, int64_t n, uint8_t *out_masks);
+
+/* Wait until the last run has finished, then write each of its requests'
+ * completion time, in microseconds after the batch started on the device,
+ * to latency_us (host, n entries; n must equal that run's size).  A
+ * request completes when the last part of its tile has been written. */
+int hv_batcher_latency(hv_batcher *b, double *latency_us, int64_t n);
+
+/* Release a batcher (NULL-safe); waits for its runs first. */
+void hv_batcher_free(hv_batcher *b);
+
+/* Time a set of launch shapes on a sample batch and return the fastest in
+ * *best (and its time per launch in *best_ms, may be NULL).  The result is
+ * also cached under the sample's class -- dominant kind, zoom band (z / 4)
+ * and radius band (r <= 1, <= 2, <= 4, > 4) -- which hv_render_batch with
+ * launch == NULL then uses for batches of that class.  scratch_masks:
+ * device, n * 8192 bytes.  Synchronous. */
+int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_launch *best, double *best_ms);
+
+/* The cached shape for a batch's class: HV_OK and *out filled, or HV_EINVAL
+ * if that class has not been tuned. */
+int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
+
 #ifdef __cplusplus
 }
 #endif

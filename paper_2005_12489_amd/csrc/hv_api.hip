@@ -4,20 +4,16 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstring>
 #include <cmath>
+#include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/hv.h"
 #include "hv_internal.h"
 
-struct hv_index {
-    hv::IndexArrays a;
-    int kind = 0;
-    int device = 0;
-    double root[4] = {0, 0, 0, 0};
-    double build_ms = 0;
-};
 
 namespace {
 
@@ -154,7 +150,7 @@ int run_batch(const hv::DevIndex *ixs, int n_ix, int max_levels, const hv::DevRe
     const hv::Workspace w = hv::workspace_layout(n_req, n_ix);
     hipError_t e = t_stage.acquire(w.staged_bytes());
     if (e != hipSuccess) return hip_status(e, who);
-    hv::stage_host(w, ixs, n_ix, reqs, n_req, t_stage.p);
+    hv::stage_host(w, ixs, n_ix, reqs, n_req, out, t_stage.p);
     unsigned char *dws = nullptr;
     e = hipMallocAsync((void **)&dws, w.total, t_stream);
     if (e != hipSuccess) return hip_status(e, who);
@@ -162,12 +158,114 @@ int run_batch(const hv::DevIndex *ixs, int n_ix, int max_levels, const hv::DevRe
     if (e == hipSuccess) e = hipEventRecord(t_stage.ev, t_stream);
     if (e == hipSuccess) {
         t_stage.pending = true;
-        e = hv::launch_query(w, dws, n_req, max_levels, out, shape, t_stream);
+        e = hv::launch_query(w, dws, max_levels, shape, t_stream);
     }
     const hipError_t ef = hipFreeAsync(dws, t_stream);
     if (e != hipSuccess) return hip_status(e, who);
     if (ef != hipSuccess) return hip_status(ef, who);
     return HV_OK;
+}
+
+int validate_tile(int32_t z, int32_t x, int32_t y, int64_t k) {
+    if (z < 0 || z > HV_MAX_ZOOM) return fail(HV_EINVAL, "request " + std::to_string(k) + ": zoom outside [0, 22]");
+    const int64_t side = int64_t(1) << z;
+    if (x < 0 || y < 0 || x >= side || y >= side)
+        return fail(HV_EINVAL, "request " + std::to_string(k) + ": x or y outside [0, 2^z)");
+    return HV_OK;
+}
+
+int validate_r(double r, int64_t k) {
+    if (!std::isfinite(r) || !(r > 0.0) || r > HV_MAX_RADIUS)
+        return fail(HV_EINVAL, "request " + std::to_string(k) + ": r_px must be finite and in (0, 64]");
+    return HV_OK;
+}
+
+int validate_out(uint8_t *out) {
+    if (!out) return fail(HV_EINVAL, "out_masks is NULL");
+    if (reinterpret_cast<uintptr_t>(out) % 16 != 0) return fail(HV_EINVAL, "out_masks must be 16-byte aligned");
+    if (!is_device_pointer(out)) return fail(HV_EINVAL, "out_masks must be device memory");
+    return HV_OK;
+}
+
+// The distinct indexes of a batch (its index table) and its requests in
+// kernel form.
+struct BatchPlan {
+    std::vector<hv::DevIndex> table;
+    std::vector<const hv_index *> owners;
+    std::vector<hv::DevReq> reqs;
+    int max_levels = 0;
+};
+
+int plan_batch(const hv_request *reqs, int64_t n, BatchPlan *p) {
+    if (n < 0) return fail(HV_EINVAL, "n < 0");
+    if (n > 0 && !reqs) return fail(HV_EINVAL, "reqs is NULL with n > 0");
+    int dev = -1;
+    bool have_dev = false;
+    p->reqs.resize((size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+        const hv_request &q = reqs[k];
+        if (!q.index) return fail(HV_EINVAL, "request " + std::to_string(k) + ": index is NULL");
+        int rc = validate_tile(q.z, q.x, q.y, k);
+        if (rc) return rc;
+        if ((rc = validate_r(q.r_px, k))) return rc;
+        int slot = -1;
+        for (int j = (int)p->owners.size() - 1; j >= 0; --j)
+            if (p->owners[(size_t)j] == q.index) {
+                slot = j;
+                break;
+            }
+        if (slot < 0) {
+            if (q.index->device >= 0) {
+                if (!have_dev) {
+                    if (hipGetDevice(&dev) != hipSuccess) return hip_status(hipGetLastError(), "hipGetDevice");
+                    have_dev = true;
+                }
+                if (dev != q.index->device)
+                    return fail(HV_EINVAL, "request " + std::to_string(k) + ": index lives on another device");
+            }
+            slot = (int)p->owners.size();
+            p->owners.push_back(q.index);
+            p->table.push_back(dev_view(q.index));
+            if (q.index->a.levels > p->max_levels) p->max_levels = q.index->a.levels;
+        }
+        p->reqs[(size_t)k] = hv::DevReq{q.z, q.x, q.y, slot, q.r_px};
+    }
+    return HV_OK;
+}
+
+// ---------------------------------------------------------------- tuning cache
+struct TuneKey {
+    int kind, zband, rband;
+    bool operator==(const TuneKey &o) const { return kind == o.kind && zband == o.zband && rband == o.rband; }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, hv_launch>> g_tune;
+
+TuneKey batch_key(const hv_request *reqs, int64_t n) {
+    int64_t seg = 0;
+    std::vector<int> zs((size_t)n);
+    std::vector<double> rs((size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+        seg += reqs[k].index->kind != HV_POINTS;
+        zs[(size_t)k] = reqs[k].z;
+        rs[(size_t)k] = reqs[k].r_px;
+    }
+    std::nth_element(zs.begin(), zs.begin() + n / 2, zs.end());
+    std::nth_element(rs.begin(), rs.begin() + n / 2, rs.end());
+    const double rm = rs[(size_t)(n / 2)];
+    return TuneKey{seg * 2 >= n ? 1 : 0, zs[(size_t)(n / 2)] / 4, rm <= 1.0 ? 0 : rm <= 2.0 ? 1 : rm <= 4.0 ? 2 : 3};
+}
+
+bool tuned_for(const hv_request *reqs, int64_t n, hv_launch *out) {
+    if (n <= 0) return false;
+    const TuneKey key = batch_key(reqs, n);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (auto &e : g_tune)
+        if (e.first == key) {
+            *out = e.second;
+            return true;
+        }
+    return false;
 }
 
 }  // namespace
@@ -323,6 +421,251 @@ int hv_index_read(const hv_index *index, int what, int level, void *host_dst, in
     const hipError_t e = hipMemcpy(host_dst, src, (size_t)need, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_status(e, "hv_index_read");
     return HV_OK;
+}
+
+
+int hv_render_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch) {
+    BatchPlan p;
+    int rc = plan_batch(reqs, n, &p);
+    if (rc) return rc;
+    hv_launch tuned;
+    if (!launch && tuned_for(reqs, n, &tuned)) launch = &tuned;
+    hv::LaunchShape shape;
+    if ((rc = resolve_shape(launch, p.max_levels, &shape))) return rc;
+    if (n == 0) {
+        t_err.clear();
+        return HV_OK;
+    }
+    if ((rc = validate_out(out_masks))) return rc;
+    rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_masks, shape,
+                   "hv_render_batch");
+    if (rc) return rc;
+    t_err.clear();
+    return HV_OK;
+}
+
+int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out) {
+    if (!out || n <= 0 || !reqs) return fail(HV_EINVAL, "NULL argument or empty batch");
+    for (int64_t k = 0; k < n; ++k)
+        if (!reqs[k].index) return fail(HV_EINVAL, "request " + std::to_string(k) + ": index is NULL");
+    if (!tuned_for(reqs, n, out)) return fail(HV_EINVAL, "no tuned shape for this batch class");
+    return HV_OK;
+}
+
+int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_launch *best, double *best_ms) {
+    if (!best) return fail(HV_EINVAL, "best is NULL");
+    if (n <= 0) return fail(HV_EINVAL, "the sample is empty");
+    BatchPlan p;
+    int rc = plan_batch(sample, n, &p);
+    if (rc) return rc;
+    if ((rc = validate_out(scratch_masks))) return rc;
+    // candidate shapes: region mode (side, waves, objects per lane, queue)
+    // and one wave per block (side, waves, stage capacity)
+    static const hv_launch cands[] = {
+        {0, 64, 1, 0, 32, 1},  {0, 128, 1, 0, 32, 2}, {0, 128, 2, 0, 32, 1}, {0, 256, 2, 0, 32, 2},
+        {0, 256, 4, 0, 32, 1}, {0, 128, 2, 0, 64, 1}, {0, 256, 2, 0, 64, 2}, {0, 256, 4, 0, 64, 1},
+        {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},  {16, 128, 4, 0, 0, 1},
+        {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},  {32, 64, 2, 0, 0, 1},
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_status(e, "hv_autotune");
+    double best_t = 1e300;
+    int best_k = -1;
+    for (int k = 0; k < (int)(sizeof(cands) / sizeof(cands[0])); ++k) {
+        hv::LaunchShape shape;
+        if (resolve_shape(&cands[k], p.max_levels, &shape)) continue;  // does not fit this batch
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+            if ((e = hipEventRecord(e0, t_stream)) != hipSuccess) break;
+            rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, scratch_masks,
+                           shape, "hv_autotune");
+            if (rc) break;
+            if ((e = hipEventRecord(e1, t_stream)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (rep > 0 && ms < ms_min) ms_min = ms;  // the first run warms up
+        }
+        if (rc || e != hipSuccess) break;
+        if (ms_min < best_t) {
+            best_t = ms_min;
+            best_k = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_status(e, "hv_autotune");
+    if (best_k < 0) return fail(HV_EINVAL, "no candidate shape fits this batch");
+    *best = cands[best_k];
+    if (best_ms) *best_ms = best_t;
+    const TuneKey key = batch_key(sample, n);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    bool found = false;
+    for (auto &x : g_tune)
+        if (x.first == key) {
+            x.second = *best;
+            found = true;
+        }
+    if (!found) g_tune.push_back({key, *best});
+    t_err.clear();
+    return HV_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batcher
+struct hv_batcher {
+    struct Slot {
+        unsigned char *host = nullptr;  // pinned staging
+        unsigned char *dev = nullptr;   // device workspace
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+        int64_t n = 0;
+    };
+    int64_t max_req = 0;
+    int max_ix = 0, max_levels = 0, device = 0;
+    hv::LaunchShape shape{};
+    hv::Workspace w{};
+    hipStream_t capture = nullptr;
+    Slot slot[2];
+    int next = 0, last = -1;
+    double khz = 0;  // wall clock rate
+};
+
+namespace {
+
+void batcher_release(hv_batcher *b) {
+    for (auto &s : b->slot) {
+        if (s.pending) (void)hipEventSynchronize(s.done);
+        if (s.exec) (void)hipGraphExecDestroy(s.exec);
+        if (s.graph) (void)hipGraphDestroy(s.graph);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.host) (void)hipHostFree(s.host);
+    }
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+hv_batcher *hv_batcher_create(int64_t max_requests, int32_t max_indexes, int32_t max_levels,
+                              const hv_launch *launch) {
+    if (max_requests < 1 || max_requests > (int64_t(1) << 24)) {
+        fail(HV_EINVAL, "max_requests must be in [1, 2^24]");
+        return nullptr;
+    }
+    if (max_indexes < 1 || max_indexes > 4096) {
+        fail(HV_EINVAL, "max_indexes must be in [1, 4096]");
+        return nullptr;
+    }
+    if (max_levels < 1 || max_levels > hv::kMaxLevels) {
+        fail(HV_EINVAL, "max_levels must be in [1, 16]");
+        return nullptr;
+    }
+    hv::LaunchShape shape;
+    if (resolve_shape(launch, max_levels, &shape)) return nullptr;
+    hv_batcher *b = new (std::nothrow) hv_batcher;
+    if (!b) {
+        fail(HV_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    b->max_req = max_requests;
+    b->max_ix = max_indexes;
+    b->max_levels = max_levels;
+    b->shape = shape;
+    b->w = hv::workspace_layout(max_requests, max_indexes);
+    hipError_t e = hipGetDevice(&b->device);
+    int khz = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device);
+    b->khz = khz;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    (void)hv::persistent_grid(shape, max_levels);  // occupancy query outside the capture
+    for (auto &s : b->slot) {
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s.host, b->w.staged_bytes(), hipHostMallocDefault);
+        if (e == hipSuccess) {
+            std::memset(s.host, 0, b->w.staged_bytes());
+            e = hipMalloc((void **)&s.dev, b->w.total);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t ec = hipMemcpyAsync(s.dev, s.host, b->w.staged_bytes(), hipMemcpyHostToDevice, b->capture);
+            if (ec == hipSuccess) ec = hv::launch_query(b->w, s.dev, max_levels, shape, b->capture);
+            e = hipStreamEndCapture(b->capture, &s.graph);
+            if (ec != hipSuccess) e = ec;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        hip_status(e, "hv_batcher_create");
+        batcher_release(b);
+        return nullptr;
+    }
+    t_err.clear();
+    return b;
+}
+
+int hv_batcher_run(hv_batcher *b, const hv_request *reqs, int64_t n, uint8_t *out_masks) {
+    if (!b) return fail(HV_EINVAL, "batcher is NULL");
+    if (n > b->max_req) return fail(HV_EINVAL, "n exceeds the batcher's max_requests");
+    BatchPlan p;
+    int rc = plan_batch(reqs, n, &p);
+    if (rc) return rc;
+    if ((int)p.table.size() > b->max_ix) return fail(HV_EINVAL, "the batch names more indexes than max_indexes");
+    if (p.max_levels > b->max_levels) return fail(HV_EINVAL, "an index is deeper than max_levels");
+    if (n > 0 && (rc = validate_out(out_masks))) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(HV_EINVAL, "the current device is not the batcher's device");
+    hv_batcher::Slot &s = b->slot[b->next];
+    if (s.pending) {
+        const hipError_t e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return hip_status(e, "hv_batcher_run");
+        s.pending = false;
+    }
+    hv::stage_host(b->w, p.table.data(), (int)p.table.size(), p.reqs.data(), n, out_masks, s.host);
+    hipError_t e = hipGraphLaunch(s.exec, t_stream);
+    if (e == hipSuccess) e = hipEventRecord(s.done, t_stream);
+    if (e != hipSuccess) return hip_status(e, "hv_batcher_run");
+    s.pending = true;
+    s.n = n;
+    b->last = b->next;
+    b->next ^= 1;
+    t_err.clear();
+    return HV_OK;
+}
+
+int hv_batcher_latency(hv_batcher *b, double *latency_us, int64_t n) {
+    if (!b || (!latency_us && n > 0)) return fail(HV_EINVAL, "NULL argument");
+    if (b->last < 0) return fail(HV_EINVAL, "the batcher has not run");
+    hv_batcher::Slot &s = b->slot[b->last];
+    if (n != s.n) return fail(HV_EINVAL, "n differs from the last run's size");
+    hipError_t e = s.pending ? hipEventSynchronize(s.done) : hipSuccess;
+    if (e != hipSuccess) return hip_status(e, "hv_batcher_latency");
+    s.pending = false;
+    if (n == 0) return HV_OK;
+    hv::BatchHeader h;
+    std::vector<uint64_t> ts((size_t)n);
+    e = hipMemcpy(&h, s.dev + b->w.hdr_off, sizeof h, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ts.data(), s.dev + b->w.ts_off, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_status(e, "hv_batcher_latency");
+    for (int64_t k = 0; k < n; ++k) {
+        const double ticks = ts[(size_t)k] > h.t_start ? (double)(ts[(size_t)k] - h.t_start) : 0.0;
+        latency_us[k] = ticks / b->khz * 1e3;
+    }
+    return HV_OK;
+}
+
+void hv_batcher_free(hv_batcher *b) {
+    if (b) batcher_release(b);
 }
 
 }  // extern "C"

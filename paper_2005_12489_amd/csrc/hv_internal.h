@@ -72,26 +72,59 @@ struct LaunchShape {
 // LDS bytes per workgroup for a shape and the deepest index of a batch.
 size_t query_lds_bytes(const LaunchShape &s, int max_levels);
 
-// Device workspace of one batch of n requests over n_ix indexes.  The first
-// staged_bytes() bytes (index table, requests, a zeroed counter) are copied
-// from the host; the rest (frontiers, compacted tile list) is written by the
-// kernels.
+// Header of a batch, in device memory and staged from the host each launch,
+// so that a captured graph's kernel arguments never change.
+struct BatchHeader {
+    int64_t n_req;      // live requests
+    uint8_t *out;       // masks: request k at out + k * 8192
+    int32_t counter;    // tiles appended to the compacted list (0 when staged)
+    int32_t pad;
+    uint64_t t_start;   // wall clock when the batch started on the device
+};
+
+// Device addresses of one batch's workspace (a kernel argument).
+struct DevBatch {
+    BatchHeader *hdr;
+    const DevIndex *ixs;
+    const DevReq *reqs;
+    uint32_t *frontier;  // per request: up to 256 frontier nodes
+    int32_t *fmeta;      // per request: frontier size, frontier level
+    uint32_t *list;      // compacted list of requests with data nearby
+    uint32_t *done;      // per request: parts finished
+    uint64_t *ts;        // per request: wall clock at completion
+};
+
+// Device workspace of one batch of up to n_req requests over n_ix indexes.
+// Its first staged_bytes() bytes (header, index table, requests) are copied
+// from the host; the rest is written by the kernels.
 struct Workspace {
-    size_t table_off, req_off, counter_off, frontier_off, fmeta_off, list_off, total;
+    int64_t n_req;
+    size_t hdr_off, table_off, req_off, frontier_off, fmeta_off, list_off, done_off, ts_off, total;
     size_t staged_bytes() const { return frontier_off; }
 };
 Workspace workspace_layout(int64_t n_req, int n_ix);
 
-// Fills the host part of a workspace (index table, requests, zero counter).
-void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq *reqs, int64_t n_req,
+// Fills the host part of a workspace.
+void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq *reqs, int64_t n_req, uint8_t *out,
                 unsigned char *host);
 
-// Launches the tile-frontier and persistent query kernels for a staged
-// workspace `dws` (device) on `stream`.  Masks go to out + k * 8192.
-hipError_t launch_query(const Workspace &w, unsigned char *dws, int64_t n_req, int max_levels, uint8_t *out,
-                        const LaunchShape &s, hipStream_t stream);
+DevBatch device_batch(const Workspace &w, unsigned char *dws);
+
+// Launches the tile-frontier and query kernels for a staged workspace `dws`
+// (device) on `stream`; the grids cover w.n_req requests.
+hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,
+                        hipStream_t stream);
 
 // Workgroups that fill the current device for a shape (occupancy x CUs).
 int persistent_grid(const LaunchShape &s, int max_levels);
 
 }  // namespace hv
+
+// An index as the C ABI hands it out.
+struct hv_index {
+    hv::IndexArrays a;
+    int kind = 0;
+    int device = 0;     // -1 for an empty index (no device memory)
+    double root[4] = {0, 0, 0, 0};
+    double build_ms = 0;
+};

@@ -65,18 +65,16 @@ __device__ inline bool meets(const double4 &nb, double qx0, double qx1, double q
     return nb.x <= qx1 && nb.z >= qx0 && nb.y <= qy1 && nb.w >= qy0;
 }
 
-__global__ __launch_bounds__(256) void k_tile_frontier(const DevIndex *__restrict__ ixs,
-                                                       const DevReq *__restrict__ reqs, int64_t n_req,
-                                                       uint32_t *__restrict__ frontier, int32_t *__restrict__ fmeta,
-                                                       int *__restrict__ counter, uint32_t *__restrict__ list,
-                                                       uint8_t *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
     __shared__ uint32_t buf[4][2][kFrontier];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps per-tile values scalar
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.hdr->t_start = wall_clock64();
     const int64_t t = (int64_t)blockIdx.x * 4 + wv;
-    if (t >= n_req) return;
-    const DevReq rq = reqs[t];
-    const DevIndex ix = ixs[rq.index];
+    if (t >= B.hdr->n_req) return;
+    uint8_t *const out = B.hdr->out;
+    const DevReq rq = B.reqs[t];
+    const DevIndex ix = B.ixs[rq.index];
     const double iS = ldexp(1.0, -8 - rq.z);
     const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
     const double m = rq.r + kCullPad;
@@ -119,14 +117,21 @@ __global__ __launch_bounds__(256) void k_tile_frontier(const DevIndex *__restric
         // no data within r of the tile: the whole mask is zero
         uint4 *m4 = reinterpret_cast<uint4 *>(out + t * (int64_t)HV_MASK_BYTES);
         for (int k = lane; k < HV_MASK_BYTES / 16; k += 64) m4[k] = make_uint4(0, 0, 0, 0);
+        if (lane == 0) B.ts[t] = wall_clock64();
         return;
     }
-    for (int k = lane; k < ncur; k += 64) frontier[t * kFrontier + k] = cur[k];
+    for (int k = lane; k < ncur; k += 64) B.frontier[t * kFrontier + k] = cur[k];
     if (lane == 0) {
-        fmeta[2 * t] = ncur;
-        fmeta[2 * t + 1] = lvl;
-        list[atomicAdd(counter, 1)] = (uint32_t)t;
+        B.fmeta[2 * t] = ncur;
+        B.fmeta[2 * t + 1] = lvl;
+        B.done[t] = 0;
+        B.list[atomicAdd(&B.hdr->counter, 1)] = (uint32_t)t;
     }
+}
+
+// Counts one finished part of request t; the last part stamps its completion.
+__device__ inline void part_done(const DevBatch &B, int64_t t, uint32_t parts) {
+    if (atomicAdd(&B.done[t], 1u) == parts - 1u) B.ts[t] = wall_clock64();
 }
 
 struct WaveLds {
@@ -397,11 +402,7 @@ __device__ __forceinline__ void block_query(const DevIndex &ix, const DevReq &rq
 }
 
 template <int BS>
-__global__ __launch_bounds__(256) void k_query(const DevIndex *__restrict__ ixs, const DevReq *__restrict__ reqs,
-                                               const uint32_t *__restrict__ frontier,
-                                               const int32_t *__restrict__ fmeta, const int *__restrict__ counter,
-                                               const uint32_t *__restrict__ list, uint8_t *__restrict__ out,
-                                               int cap, int max_levels) {
+__global__ __launch_bounds__(256) void k_query(DevBatch B, int cap, int max_levels) {
     extern __shared__ double4 smem[];
     constexpr int BPT = (256 / BS) * (256 / BS);
     const int lane = threadIdx.x & 63;
@@ -419,15 +420,17 @@ __global__ __launch_bounds__(256) void k_query(const DevIndex *__restrict__ ixs,
 
     // a workgroup's waves take consecutive blocks of one tile
     const int per_wg = (BPT + wpb - 1) / wpb;
-    const ItemMap im(*counter, per_wg);
+    uint8_t *const out = B.hdr->out;
+    const ItemMap im(B.hdr->counter, per_wg);
     for (int64_t u = im.first; u < im.n; u += im.step) {
         const int b = (int)(u % per_wg) * wpb + wv;
         if (b >= BPT) continue;
-        const int64_t t = list[im.pos(u, per_wg)];
-        const DevReq rq = reqs[t];
-        const DevIndex ix = ixs[rq.index];
-        if (ix.seg) block_query<BS, 1>(ix, rq, t, b, frontier, fmeta, out, cap, L, lane);
-        else block_query<BS, 0>(ix, rq, t, b, frontier, fmeta, out, cap, L, lane);
+        const int64_t t = B.list[im.pos(u, per_wg)];
+        const DevReq rq = B.reqs[t];
+        const DevIndex ix = B.ixs[rq.index];
+        if (ix.seg) block_query<BS, 1>(ix, rq, t, b, B.frontier, B.fmeta, out, cap, L, lane);
+        else block_query<BS, 0>(ix, rq, t, b, B.frontier, B.fmeta, out, cap, L, lane);
+        if (lane == 0) part_done(B, t, BPT);
     }
 }
 
@@ -706,13 +709,7 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
 }
 
 template <int RS, int OPL>
-__global__ __launch_bounds__(256) void k_query_region(const DevIndex *__restrict__ ixs,
-                                                      const DevReq *__restrict__ reqs,
-                                                      const uint32_t *__restrict__ frontier,
-                                                      const int32_t *__restrict__ fmeta,
-                                                      const int *__restrict__ counter,
-                                                      const uint32_t *__restrict__ list, uint8_t *__restrict__ out,
-                                                      int cap, int max_levels) {
+__global__ __launch_bounds__(256) void k_query_region(DevBatch B, int cap, int max_levels) {
     extern __shared__ double4 smem[];
     constexpr int RPT = (256 / RS) * (256 / RS);
     unsigned char *base = reinterpret_cast<unsigned char *>(smem);
@@ -727,19 +724,20 @@ __global__ __launch_bounds__(256) void k_query_region(const DevIndex *__restrict
     L.mask = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.cpre) + align16((size_t)(cap + 1) * 4));
     L.ctl = reinterpret_cast<int *>(L.mask + RS * (RS / 32));
     L.scan = reinterpret_cast<uint32_t *>(L.ctl + 4);
-    const ItemMap im(*counter, RPT);
+    uint8_t *const out = B.hdr->out;
+    const ItemMap im(B.hdr->counter, RPT);
     for (int64_t u = im.first; u < im.n; u += im.step) {
-        const int64_t t = list[im.pos(u, RPT)];
+        const int64_t t = B.list[im.pos(u, RPT)];
         const int reg = (int)(u % RPT);
-        const DevReq rq = reqs[t];
-        const DevIndex ix = ixs[rq.index];
-        if (ix.seg) region_query<RS, 1, OPL>(ix, rq, t, reg, frontier, fmeta, out, cap, L);
-        else region_query<RS, 0, OPL>(ix, rq, t, reg, frontier, fmeta, out, cap, L);
+        const DevReq rq = B.reqs[t];
+        const DevIndex ix = B.ixs[rq.index];
+        if (ix.seg) region_query<RS, 1, OPL>(ix, rq, t, reg, B.frontier, B.fmeta, out, cap, L);
+        else region_query<RS, 0, OPL>(ix, rq, t, reg, B.frontier, B.fmeta, out, cap, L);
+        if (threadIdx.x == 0) part_done(B, t, RPT);
     }
 }
 
-using RegionKernel = void (*)(const DevIndex *, const DevReq *, const uint32_t *, const int32_t *, const int *,
-                             const uint32_t *, uint8_t *, int, int);
+using RegionKernel = void (*)(DevBatch, int, int);
 
 RegionKernel region_kernel(const LaunchShape &s) {
     if (s.region == 32) return s.opl == 4 ? k_query_region<32, 4> : s.opl == 2 ? k_query_region<32, 2> : k_query_region<32, 1>;
@@ -761,21 +759,41 @@ size_t query_lds_bytes(const LaunchShape &s, int max_levels) {
 
 Workspace workspace_layout(int64_t n_req, int n_ix) {
     Workspace w;
-    w.table_off = 0;
-    w.req_off = align256(sizeof(DevIndex) * (size_t)n_ix);
-    w.counter_off = w.req_off + align256(sizeof(DevReq) * (size_t)n_req);
-    w.frontier_off = w.counter_off + 256;
+    w.n_req = n_req;
+    w.hdr_off = 0;
+    w.table_off = 256;
+    w.req_off = w.table_off + align256(sizeof(DevIndex) * (size_t)n_ix);
+    w.frontier_off = w.req_off + align256(sizeof(DevReq) * (size_t)n_req);
     w.fmeta_off = w.frontier_off + align256(sizeof(uint32_t) * kFrontier * (size_t)n_req);
     w.list_off = w.fmeta_off + align256(sizeof(int32_t) * 2 * (size_t)n_req);
-    w.total = w.list_off + align256(sizeof(uint32_t) * (size_t)n_req);
+    w.done_off = w.list_off + align256(sizeof(uint32_t) * (size_t)n_req);
+    w.ts_off = w.done_off + align256(sizeof(uint32_t) * (size_t)n_req);
+    w.total = w.ts_off + align256(sizeof(uint64_t) * (size_t)n_req);
     return w;
 }
 
-void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq *reqs, int64_t n_req,
+void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq *reqs, int64_t n_req, uint8_t *out,
                 unsigned char *host) {
+    BatchHeader h;
+    memset(&h, 0, sizeof h);
+    h.n_req = n_req;
+    h.out = out;
+    memcpy(host + w.hdr_off, &h, sizeof h);
     memcpy(host + w.table_off, ixs, sizeof(DevIndex) * (size_t)n_ix);
     memcpy(host + w.req_off, reqs, sizeof(DevReq) * (size_t)n_req);
-    memset(host + w.counter_off, 0, 256);
+}
+
+DevBatch device_batch(const Workspace &w, unsigned char *dws) {
+    DevBatch b;
+    b.hdr = reinterpret_cast<BatchHeader *>(dws + w.hdr_off);
+    b.ixs = reinterpret_cast<const DevIndex *>(dws + w.table_off);
+    b.reqs = reinterpret_cast<const DevReq *>(dws + w.req_off);
+    b.frontier = reinterpret_cast<uint32_t *>(dws + w.frontier_off);
+    b.fmeta = reinterpret_cast<int32_t *>(dws + w.fmeta_off);
+    b.list = reinterpret_cast<uint32_t *>(dws + w.list_off);
+    b.done = reinterpret_cast<uint32_t *>(dws + w.done_off);
+    b.ts = reinterpret_cast<uint64_t *>(dws + w.ts_off);
+    return b;
 }
 
 int persistent_grid(const LaunchShape &s, int max_levels) {
@@ -807,17 +825,12 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
     return grid;
 }
 
-hipError_t launch_query(const Workspace &w, unsigned char *dws, int64_t n_req, int max_levels, uint8_t *out,
-                        const LaunchShape &s, hipStream_t st) {
+hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,
+                        hipStream_t st) {
+    const int64_t n_req = w.n_req;  // requests the grids cover; the header holds how many are live
     if (n_req == 0) return hipSuccess;
-    const DevIndex *ixs = reinterpret_cast<const DevIndex *>(dws + w.table_off);
-    const DevReq *reqs = reinterpret_cast<const DevReq *>(dws + w.req_off);
-    int *counter = reinterpret_cast<int *>(dws + w.counter_off);
-    uint32_t *frontier = reinterpret_cast<uint32_t *>(dws + w.frontier_off);
-    int32_t *fmeta = reinterpret_cast<int32_t *>(dws + w.fmeta_off);
-    uint32_t *list = reinterpret_cast<uint32_t *>(dws + w.list_off);
-    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, ixs, reqs, n_req,
-                       frontier, fmeta, counter, list, out);
+    const DevBatch B = device_batch(w, dws);
+    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B);
     const size_t lds = query_lds_bytes(s, max_levels);
     // never more workgroups than there are blocks (or regions) to render
     const int64_t per_tile = s.region ? (256 / s.region) * (256 / s.region)
@@ -827,18 +840,10 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int64_t n_req, i
     int64_t grid = s.grid > 0 ? s.grid : persistent_grid(s, max_levels);
     if (grid > need) grid = need;
     const dim3 g((uint32_t)grid), b((uint32_t)(64 * s.waves));
-    if (s.region)
-        hipLaunchKernelGGL(region_kernel(s), g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out,
-                           s.cand_cap, max_levels);
-    else if (s.block == 8)
-        hipLaunchKernelGGL(k_query<8>, g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out, s.cand_cap,
-                           max_levels);
-    else if (s.block == 16)
-        hipLaunchKernelGGL(k_query<16>, g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out, s.cand_cap,
-                           max_levels);
-    else
-        hipLaunchKernelGGL(k_query<32>, g, b, lds, st, ixs, reqs, frontier, fmeta, counter, list, out, s.cand_cap,
-                           max_levels);
+    if (s.region) hipLaunchKernelGGL(region_kernel(s), g, b, lds, st, B, s.cand_cap, max_levels);
+    else if (s.block == 8) hipLaunchKernelGGL(k_query<8>, g, b, lds, st, B, s.cand_cap, max_levels);
+    else if (s.block == 16) hipLaunchKernelGGL(k_query<16>, g, b, lds, st, B, s.cand_cap, max_levels);
+    else hipLaunchKernelGGL(k_query<32>, g, b, lds, st, B, s.cand_cap, max_levels);
     return hipGetLastError();
 }
 

@@ -39,7 +39,12 @@ HV_MASK_BYTES = 8192
 HV_MAX_ZOOM = 22
 
 SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free", "hv_last_error",
-           "hv_set_stream", "hv_index_info", "hv_index_read")
+           "hv_set_stream", "hv_index_info", "hv_index_read", "hv_render_batch", "hv_batcher_create",
+           "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch")
+
+# hv_request as a numpy record (32 bytes, the C layout)
+REQUEST_DTYPE = np.dtype([("index", np.uint64), ("z", np.int32), ("x", np.int32), ("y", np.int32),
+                          ("pad", np.int32), ("r_px", np.float64)])
 
 
 class hv_tile(ctypes.Structure):
@@ -91,6 +96,22 @@ lib.hv_index_info.restype = ctypes.c_int
 lib.hv_index_info.argtypes = [_P, ctypes.POINTER(hv_info)]
 lib.hv_index_read.restype = ctypes.c_int
 lib.hv_index_read.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64]
+
+
+lib.hv_render_batch.restype = ctypes.c_int
+lib.hv_render_batch.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
+lib.hv_batcher_create.restype = _P
+lib.hv_batcher_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(hv_launch)]
+lib.hv_batcher_run.restype = ctypes.c_int
+lib.hv_batcher_run.argtypes = [_P, _P, ctypes.c_int64, _P]
+lib.hv_batcher_latency.restype = ctypes.c_int
+lib.hv_batcher_latency.argtypes = [_P, _P, ctypes.c_int64]
+lib.hv_batcher_free.restype = None
+lib.hv_batcher_free.argtypes = [_P]
+lib.hv_autotune.restype = ctypes.c_int
+lib.hv_autotune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.POINTER(ctypes.c_double)]
+lib.hv_tuned_launch.restype = ctypes.c_int
+lib.hv_tuned_launch.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(hv_launch)]
 
 
 def _check(rc: int) -> int:
@@ -203,6 +224,85 @@ def hv_index_read(index: int, what: int, level: int = 0) -> np.ndarray:
         raise HvError(HV_EINVAL, "unknown array")
     _check(lib.hv_index_read(index, what, level, out.ctypes.data_as(_P), out.nbytes))
     return out
+
+
+def requests(indexes, tiles, r) -> np.ndarray:
+    """Builds an hv_request array: indexes (handles, one per request or one
+    for all), tiles (n,3) z,x,y, r (scalar or n)."""
+    t = np.asarray(tiles, dtype=np.int64).reshape(-1, 3)
+    n = t.shape[0]
+    out = np.zeros(n, dtype=REQUEST_DTYPE)
+    out["index"] = np.broadcast_to(np.asarray(indexes, dtype=np.uint64), (n,))
+    out["z"], out["x"], out["y"] = t[:, 0], t[:, 1], t[:, 2]
+    out["r_px"] = np.broadcast_to(np.asarray(r, dtype=np.float64), (n,))
+    return out
+
+
+def _reqs(reqs) -> np.ndarray:
+    r = np.ascontiguousarray(reqs)
+    if r.dtype != REQUEST_DTYPE:
+        raise HvError(HV_EINVAL, "requests must be built with hv.requests()")
+    return r
+
+
+def _launch(launch):
+    if launch is None:
+        return None
+    return launch if isinstance(launch, hv_launch) else hv_launch(**launch)
+
+
+def hv_render_batch(reqs, out_masks, launch=None) -> None:
+    r = _reqs(reqs)
+    L = _launch(launch)
+    _sync_stream()
+    _check(lib.hv_render_batch(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks),
+                               ctypes.byref(L) if L else None))
+
+
+def hv_batcher_create(max_requests: int, max_indexes: int = 8, max_levels: int = 10, launch=None) -> int:
+    L = _launch(launch)
+    h = lib.hv_batcher_create(int(max_requests), int(max_indexes), int(max_levels), ctypes.byref(L) if L else None)
+    if not h:
+        raise HvError(HV_EINVAL, hv_last_error())
+    return h
+
+
+def hv_batcher_run(batcher: int, reqs, out_masks) -> None:
+    r = _reqs(reqs)
+    _sync_stream()
+    _check(lib.hv_batcher_run(batcher, r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks)))
+
+
+def hv_batcher_latency(batcher: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.float64)
+    _check(lib.hv_batcher_latency(batcher, out.ctypes.data_as(_P), int(n)))
+    return out
+
+
+def hv_batcher_free(batcher: int | None) -> None:
+    lib.hv_batcher_free(batcher)
+
+
+def _launch_dict(L: hv_launch) -> dict:
+    return {k: getattr(L, k) for k, _ in hv_launch._fields_}
+
+
+def hv_autotune(reqs, scratch_masks):
+    """Returns (best launch as a dict, its time per launch in ms)."""
+    r = _reqs(reqs)
+    best = hv_launch()
+    ms = ctypes.c_double(0.0)
+    _sync_stream()
+    _check(lib.hv_autotune(r.ctypes.data_as(_P), r.shape[0], _device_ptr(scratch_masks), ctypes.byref(best),
+                           ctypes.byref(ms)))
+    return _launch_dict(best), ms.value
+
+
+def hv_tuned_launch(reqs):
+    r = _reqs(reqs)
+    L = hv_launch()
+    rc = lib.hv_tuned_launch(r.ctypes.data_as(_P), r.shape[0], ctypes.byref(L))
+    return _launch_dict(L) if rc == HV_OK else None
 
 
 # ------------------------------------------------------------ convenience

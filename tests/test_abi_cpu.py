@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported(hv):
     exported = set(re.findall(r"\bT (hv_[a-z_]+)\b", out))
     missing = [n for n in names if n not in exported]
     assert not missing, missing
-    assert set(hv.SYMBOLS) == set(names)
+    assert set(hv.SYMBOLS) == set(names), sorted(set(names) ^ set(hv.SYMBOLS))
 
 
 def test_build_rejects_bad_arguments(hv):
@@ -84,5 +84,28 @@ def test_render_rejects_host_output_and_bad_shapes(hv):
         with pytest.raises(hv.HvError, match="NULL"):
             hv.hv_render_tiles(h, [(3, 1, 1)], 1.0, 0)
         assert (buf == 0).all()
+    finally:
+        hv.hv_free(h)
+
+
+def test_batch_validation_before_any_device_call(hv):
+    h = hv.hv_index_build(None, hv.HV_POINTS, 0)
+    try:
+        for reqs, msg in [(hv.requests(0, [(3, 1, 1)], 1.0), "index is NULL"),
+                          (hv.requests(h, [(3, 1, 1), (23, 0, 0)], 1.0), "request 1: zoom"),
+                          (hv.requests(h, [(3, 8, 1)], 1.0), "x or y"),
+                          (hv.requests(h, [(3, 1, 1)], 0.0), "r_px")]:
+            with pytest.raises(hv.HvError, match=msg):
+                hv.hv_render_batch(reqs, 1)
+        with pytest.raises(hv.HvError, match="NULL"):
+            hv.hv_render_batch(hv.requests(h, [(3, 1, 1)], 1.0), 0)
+        hv.hv_render_batch(hv.requests(h, np.zeros((0, 3)), 1.0), 0)       # empty batch
+        for args, msg in [((0,), "max_requests"), ((10, 0), "max_indexes"), ((10, 1, 0), "max_levels"),
+                          ((10, 1, 17), "max_levels")]:
+            with pytest.raises(hv.HvError, match=msg):
+                hv.hv_batcher_create(*args)
+        with pytest.raises(hv.HvError, match="empty"):
+            hv.hv_autotune(hv.requests(h, np.zeros((0, 3)), 1.0), 1)
+        assert hv.hv_tuned_launch(hv.requests(h, [(3, 1, 1)], 1.0)) is None
     finally:
         hv.hv_free(h)
