@@ -1,18 +1,30 @@
-"""Tile-mask throughput on one MI355X.
+"""Tile-mask throughput on one MI355X.  Prints one JSON line.
 
-One step renders every tile of the workload (one launch through
-hv_render_tiles, the index resident in HBM).  Prints one JSON line.
+One step renders every request of the workload in one batched launch: a
+HIP graph [copy the staged requests -> tile-frontier kernel -> query kernel]
+replayed by hv_batcher, with the index already resident in HBM.
 
-Default workload: 10,000,000 linestring segments (random-walk polylines,
-64-centre mixture), all 4,096 tiles of zoom 6, line width 1 px (r = 0.5).
-Also reported: the same tiles rendered with one launch per tile (p50/p99
-per-tile latency), the index build time, the query kernel against the HBM
-roofline (algorithmic bytes per launch from the oracle's work counters), and
-the CPU oracle timed on a bounded sample of the same tiles.
+Workloads (--workload):
+  c2 (default)  10,000,000 linestring segments (random-walk polylines,
+                64-centre mixture); all 4,096 tiles of zoom 6; width 1 px.
+  c1            10,000 uniform points; all 256 tiles of zoom 4; radius 2 px.
+  c3            1e9 clustered points; 10,000 density-proportional tiles at
+                zooms 0-18, radius 1-3 px.
+  c4            >= 2e8 star-polygon edges; 4,096 mixed requests per launch at
+                zooms 2-20, widths 1-5 px.
+
+Reported beside the batched figure: per-request latency p50/p99 inside a
+batch (device completion stamps), the same requests as one plain
+hv_render_batch call, and as one launch per request (p50/p99 of each
+launch); the index build time; the query kernels against the HBM roofline
+(algorithmic bytes per launch from the oracle's work counters, and HBM
+traffic from committed rocprofv3 counters while the query source is
+unchanged); and the CPU oracle timed on a bounded sample of the workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,46 +41,96 @@ METRIC = "256×256 tiles/sec at 1 GPU + p50/p99 tile latency; batched vs per-til
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 WORK_FILE = os.path.join(ROOT, "tests", "golden", "algorithmic_work.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_query_linestrings10M_z6.json")
+QUERY_SOURCE = os.path.join(ROOT, "paper_2005_12489_amd", "csrc", "hv_query.hip")
 
 WORKLOADS = {
-    "c2": dict(name="linestrings-10M-z6-all4096-w1", kind=1),
     "c1": dict(name="points-10k-z4-all256-r2", kind=0),
+    "c2": dict(name="linestrings-10M-z6-all4096-w1", kind=1),
+    "c3": dict(name="points-1e9-clustered-10000tiles-z0-18-r1-3", kind=0),
+    "c4": dict(name="polygon-edges-2e8-4096mixed-z2-20-w1-5", kind=2),
 }
 
 
-def make_workload(key: str):
+def make_workload(key: str, scale: float = 1.0):
+    """(objects, tiles (n,3), r (n,), config dict)."""
+    if key == "c1":
+        objs = hvgen.gen_c1_points()
+        tiles, r = hvgen.c1_requests()
+        cfg = {"n_points": int(objs.shape[0]), "zoom": 4, "tiles": int(len(tiles)), "r_px": r}
+        return objs, tiles, np.full(len(tiles), r), cfg
     if key == "c2":
         objs = hvgen.gen_c2_segments()
         tiles, r = hvgen.c2_requests()
         cfg = {"n_segments": int(objs.shape[0]), "zoom": 6, "tiles": int(len(tiles)), "r_px": r,
                "line_width_px": 2 * r}
-    else:
-        objs = hvgen.gen_c1_points()
-        tiles, r = hvgen.c1_requests()
-        cfg = {"n_points": int(objs.shape[0]), "zoom": 4, "tiles": int(len(tiles)), "r_px": r}
-    return objs, tiles, r, cfg
+        return objs, tiles, np.full(len(tiles), r), cfg
+    if key == "c3":
+        n = int(1_000_000_000 * scale)
+        objs = hvgen.gen_c3_points(n)
+        tiles, r = hvgen.c3_requests(10_000)
+        cfg = {"n_points": n, "zooms": "0-18", "tiles": int(len(tiles)), "r_px": "U[1,3]"}
+        return objs, tiles, r, cfg
+    if key == "c4":
+        objs = hvgen.gen_c4_edges(min_edges=int(200_000_000 * scale))
+        tiles, r = hvgen.c4_requests(objs, n=4096)
+        cfg = {"n_edges": int(objs.shape[0]), "zooms": "2-20", "requests_per_launch": int(len(tiles)),
+               "line_width_px": "U{1..5}"}
+        return objs, tiles, r, cfg
+    raise KeyError(key)
 
 
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
+def source_hash() -> str:
+    return hashlib.sha256(open(QUERY_SOURCE, "rb").read()).hexdigest()
+
+
 def cpu_baseline(objs, kind, tiles, r, seconds: float):
-    """The oracle (as it stands) on a bounded random sample of the same tiles."""
+    """The oracle (as it stands) on a bounded random sample of the requests.
+
+    For sets too large for the host oracle (above 5e7 objects) its index is
+    built over the objects that can reach the sampled tiles only."""
     import oracle
-    ix = oracle.OracleIndex(objs, kind)
-    threads = oracle.default_threads()
     order = np.random.default_rng(12345).permutation(len(tiles))
+    threads = oracle.default_threads()
+    note = ""
+    if objs.shape[0] > 50_000_000:
+        # keep the objects whose first vertex lies within one zoom-8 cell of a
+        # sampled request (a cell is 1.4 degrees wide)
+        sample = order[:64]
+        X, Y = oracle.project(objs[:, :2])
+        cell = np.minimum((Y * 256).astype(np.int32), 255) * 256 + np.minimum((X * 256).astype(np.int32), 255)
+        del X, Y
+        need = set()
+        for t in sample:
+            z, x, y = (int(v) for v in tiles[t])
+            if z >= 8:
+                x0 = x1 = x >> (z - 8)
+                y0 = y1 = y >> (z - 8)
+            else:
+                x0, x1 = x << (8 - z), ((x + 1) << (8 - z)) - 1
+                y0, y1 = y << (8 - z), ((y + 1) << (8 - z)) - 1
+            for cy in range(max(0, y0 - 1), min(255, y1 + 1) + 1):
+                for cx in range(max(0, x0 - 1), min(255, x1 + 1) + 1):
+                    need.add(cy * 256 + cx)
+        objs = objs[np.isin(cell, np.fromiter(need, dtype=np.int32))]
+        order = sample
+        note = (f"; index over the {objs.shape[0]} objects whose first vertex lies within one zoom-8 "
+                "cell of the 64 sampled requests")
+    ix = oracle.OracleIndex(objs, kind)
     done, t0 = 0, time.perf_counter()
     chunk = max(threads, 8)
-    while done < len(tiles) and time.perf_counter() - t0 < seconds:
+    while done < len(order) and time.perf_counter() - t0 < seconds:
         sel = order[done:done + chunk]
-        ix.render(tiles[sel], r, nthreads=threads, want_bit=False)
+        ix.render(tiles[sel], r[sel], nthreads=threads, want_bit=False)
         done += len(sel)
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "tiles/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} tiles drawn at random (seed 12345) from the {len(tiles)} tiles, "
-                      f"{dt:.1f} s of CPU work on {threads} threads; index build untimed"}
+            "sample": f"{done} requests drawn at random (seed 12345) from the {len(tiles)}, "
+                      f"{dt:.1f} s of CPU work on {threads} threads; index build untimed{note}"}
 
 
 def main():
@@ -77,15 +139,22 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--scale", type=float, default=1.0, help="object-count scale for c3 / c4")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-tile", action="store_true")
-    ap.add_argument("--launch", default="", help="JSON hv_launch fields, e.g. '{\"block\": 8}'")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", default="", help="JSON hv_launch fields, e.g. '{\"region\": 64}'")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes per step (HBM counter calibration)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "how the path would shard is described, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
     if args.copy_bytes:
-        import torch
         a = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         for _ in range(args.warmup + args.steps):
@@ -93,94 +162,109 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes, "steps": args.warmup + args.steps}))
         return
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU design is described but not built", file=sys.stderr)
-        sys.exit(2)
 
-    import torch
     from paper_2005_12489_amd import hv
 
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]
-    objs, tiles, r, cfg = make_workload(args.workload)
-    tiles4 = hv.tiles_array(tiles)
-    n_tiles = len(tiles4)
-    launch = json.loads(args.launch) if args.launch else None
+    objs, tiles, rr, cfg = make_workload(args.workload, args.scale)
+    n = len(tiles)
 
     d_objs = torch.from_numpy(objs).cuda()
     torch.cuda.synchronize()
     h = hv.hv_index_build(d_objs, wl["kind"])
     info = hv.hv_index_info(h)
     del d_objs
-    out = torch.empty((n_tiles, hv.HV_MASK_BYTES), dtype=torch.uint8, device="cuda")
+    torch.cuda.empty_cache()
+    reqs = hv.requests(h, tiles, rr)
+    out = torch.empty((n, hv.HV_MASK_BYTES), dtype=torch.uint8, device="cuda")
 
-    def step():
-        if launch:
-            hv.hv_render_tiles_ex(h, tiles4, r, out, launch)
-        else:
-            hv.hv_render_tiles(h, tiles4, r, out)
+    launch = json.loads(args.launch) if args.launch else None
+    tuned_ms = None
+    if launch is None and not args.no_autotune:
+        launch, tuned_ms = hv.hv_autotune(reqs, out)
 
+    # batched: one graph launch per step
+    batcher = hv.hv_batcher_create(n, max_indexes=1, max_levels=info["levels"], launch=launch)
     for _ in range(args.warmup):
-        step()
+        hv.hv_batcher_run(batcher, reqs, out)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
         evs[k][0].record()
-        step()
+        hv.hv_batcher_run(batcher, reqs, out)
         evs[k][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_ms = [a.elapsed_time(b) for a, b in evs]
+    lat_ms = hv.hv_batcher_latency(batcher, n) / 1e3
+    hv.hv_batcher_free(batcher)
     wall = t1 - t0
-    value = n_tiles * args.steps / wall
+    value = n * args.steps / wall
     kernel_ms = float(np.mean(step_ms))
+
+    # the same requests as one plain (not graph-captured) call
+    for _ in range(2):
+        hv.hv_render_batch(reqs, out, launch)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for _ in range(5):
+        hv.hv_render_batch(reqs, out, launch)
+    torch.cuda.synchronize()
+    plain = n * 5 / (time.perf_counter() - p0)
 
     per_tile = None
     if not args.no_per_tile:
-        pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_tiles)]
+        m = min(n, 4096)
+        pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(m)]
         torch.cuda.synchronize()
-        p0 = time.perf_counter()
-        for k in range(n_tiles):
+        q0 = time.perf_counter()
+        for k in range(m):
             pe[k][0].record()
-            if launch:
-                hv.hv_render_tiles_ex(h, tiles4[k:k + 1], r, out[k], launch)
-            else:
-                hv.hv_render_tiles(h, tiles4[k:k + 1], r, out[k])
+            hv.hv_render_batch(reqs[k:k + 1], out[k], launch)
             pe[k][1].record()
         torch.cuda.synchronize()
-        p1 = time.perf_counter()
+        q1 = time.perf_counter()
         lat = [a.elapsed_time(b) for a, b in pe]
-        per_tile = {"tiles_per_s": n_tiles / (p1 - p0), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-                    "launches": n_tiles}
+        per_tile = {"tiles_per_s": m / (q1 - q0), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "launches": m}
 
     roofline = None
     work = json.load(open(WORK_FILE)).get(wl["name"]) if os.path.exists(WORK_FILE) else None
     if work:
         bytes_launch = work["alg_bytes"]
         achieved = bytes_launch / (kernel_ms * 1e-3) / 1e9
+        traffic = None
+        if os.path.exists(COUNTERS_FILE):
+            c = json.load(open(COUNTERS_FILE))
+            if c.get("workload") == wl["name"] and c.get("query_source_sha256") == source_hash():
+                traffic = c["hbm_bytes_per_launch"]
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "alg_bytes_per_launch": bytes_launch,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "kernels": "k_tile_frontier + query kernel, one step",
+                    "alg_bytes_per_launch": bytes_launch, "kernel_ms": kernel_ms,
                     "fp64_tflops": work["alg_flops"] / (kernel_ms * 1e-3) / 1e12,
                     "fp64_frac": work["alg_flops"] / (kernel_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                    "kernel_ms": kernel_ms}
+                    "traffic_gbs": traffic / (kernel_ms * 1e-3) / 1e9 if traffic else None}
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(objs, wl["kind"], tiles4[:, :3], r, args.cpu_seconds)
+        cpu = cpu_baseline(objs, wl["kind"], tiles, rr, args.cpu_seconds)
 
     hv.hv_free(h)
     rec = {
         "metric": METRIC, "value": value, "unit": "tiles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": wl["name"], **cfg, "launch": launch or "default",
+        "config": {"workload": wl["name"], **cfg, "launch": launch,
                    "index": {k: info[k] for k in ("levels", "nodes", "leaf_size", "fanout", "key_bits")}},
-        "batched": {"tiles_per_s": value, "p50_ms": pct(step_ms, 50), "p99_ms": pct(step_ms, 99),
-                    "note": "one launch renders every tile; a tile's latency is the launch's"},
+        "batched": {"tiles_per_s": value, "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
+                    "step_p50_ms": pct(step_ms, 50), "step_p99_ms": pct(step_ms, 99),
+                    "note": "one graph launch per step; a request's latency is its completion "
+                            "after the batch started on the device"},
+        "plain_call_tiles_per_s": plain,
         "per_tile_launch": per_tile,
+        "autotune_ms": tuned_ms,
         "build_ms": info["build_ms"],
         "roofline": roofline,
         "cpu_baseline": cpu,

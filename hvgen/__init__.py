@@ -173,15 +173,43 @@ def gen_c3_chunk(chunk: int, chunk_size: int = 10_000_000, seed: int = 3,
     return _c3_draw(rng, chunk_size, _c3_hotspots(seed))
 
 
-def gen_c3_points(n: int, seed: int = 3, chunk_size: int = 10_000_000) -> np.ndarray:
+def _workers(jobs: int) -> int:
+    import os
+    return max(1, min(jobs, 16, len(os.sched_getaffinity(0))))
+
+
+def _c3_fill(args):
+    shm_name, n, chunk, chunk_size, seed, n_chunks = args
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(name=shm_name)
+    try:
+        out = np.ndarray((n, 2), dtype=np.float64, buffer=shm.buf)
+        lo = chunk * chunk_size
+        m = min(chunk_size, n - lo)
+        out[lo:lo + m] = gen_c3_chunk(chunk, chunk_size, seed, n_chunks)[:m]
+        del out
+    finally:
+        shm.close()
+    return chunk
+
+
+def gen_c3_points(n: int, seed: int = 3, chunk_size: int = 10_000_000, workers: int | None = None) -> np.ndarray:
+    """The clustered point set, chunk by chunk (chunks are independent, so
+    large sets are generated by parallel processes into shared memory)."""
     n_chunks = max(1, -(-n // chunk_size))
-    parts = []
-    left = n
-    for c in range(n_chunks):
-        m = min(chunk_size, left)
-        parts.append(gen_c3_chunk(c, chunk_size, seed, max(100, n_chunks))[:m])
-        left -= m
-    return np.concatenate(parts, axis=0)
+    spawn = max(100, n_chunks)
+    if n_chunks == 1:
+        return gen_c3_chunk(0, chunk_size, seed, spawn)[:n].copy()
+    from multiprocessing import get_context, shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=n * 16)
+    try:
+        with get_context("fork").Pool(workers or _workers(n_chunks)) as pool:
+            pool.map(_c3_fill, [(shm.name, n, c, chunk_size, seed, spawn) for c in range(n_chunks)])
+        out = np.ndarray((n, 2), dtype=np.float64, buffer=shm.buf).copy()
+    finally:
+        shm.close()
+        shm.unlink()
+    return out
 
 
 def c3_requests(n: int = 10_000, seed: int = 30, data_seed: int = 3, zmax: int = 18):
@@ -195,25 +223,21 @@ def c3_requests(n: int = 10_000, seed: int = 30, data_seed: int = 3, zmax: int =
 
 
 # ---------------------------------------------------------------- config 4
-def gen_c4_edges(seed: int = 4, min_edges: int = 200_000_000, n_centres: int = 256,
-                 centre_sigma: float = 2.0, batch_polygons: int = 200_000) -> np.ndarray:
-    """Star-shaped random polygons split into edges (closing edge included).
-
-    Polygon centre = one of 256 mixture centres + N(0, 2 deg); k ~ U{4..200}
-    vertices at sorted uniform angles; base radius log-normal (median 0.05
-    deg, sigma 1); vertex radius = base * U[0.5, 1].  Polygons are generated
-    until at least ``min_edges`` edges exist.
-    """
-    rng = np.random.default_rng(seed)
-    c_lon = rng.uniform(-180.0, 180.0, n_centres)
-    c_lat = rng.uniform(-80.0, 80.0, n_centres)
+def _c4_chunk(args) -> np.ndarray:
+    """Polygons of one chunk until it holds at least `target` edges."""
+    seed, chunk, n_chunks, target, n_centres, centre_sigma, batch_polygons = args
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(1 + n_chunks)
+    crng = np.random.default_rng(kids[0])
+    c_lon = crng.uniform(-180.0, 180.0, n_centres)
+    c_lat = crng.uniform(-80.0, 80.0, n_centres)
+    rng = np.random.default_rng(kids[1 + chunk])
     parts = []
     total = 0
-    while total < min_edges:
+    while total < target:
         k = rng.integers(4, 201, batch_polygons)
         cum = np.cumsum(k)
-        need = min_edges - total
-        p = min(batch_polygons, int(np.searchsorted(cum, need)) + 1)
+        p = min(batch_polygons, int(np.searchsorted(cum, target - total)) + 1)
         k = k[:p]
         ci = rng.integers(0, n_centres, p)
         px = c_lon[ci] + rng.normal(0.0, centre_sigma, p)
@@ -229,8 +253,7 @@ def gen_c4_edges(seed: int = 4, min_edges: int = 200_000_000, n_centres: int = 2
         vy = _fold(py[owner] + rad * np.sin(ang), LAT_LO, LAT_HI)
         first = np.concatenate([[0], np.cumsum(k)[:-1]])
         nxt = np.arange(nv) + 1
-        last = first + k - 1
-        nxt[last] = first                                 # closing edge
+        nxt[first + k - 1] = first                        # closing edge
         e = np.empty((nv, 4), dtype=np.float64)
         e[:, 0] = vx
         e[:, 1] = vy
@@ -238,6 +261,29 @@ def gen_c4_edges(seed: int = 4, min_edges: int = 200_000_000, n_centres: int = 2
         e[:, 3] = vy[nxt]
         parts.append(e)
         total += nv
+    return np.concatenate(parts, axis=0)
+
+
+def gen_c4_edges(seed: int = 4, min_edges: int = 200_000_000, n_centres: int = 256,
+                 centre_sigma: float = 2.0, batch_polygons: int = 200_000, chunk_edges: int = 10_000_000,
+                 workers: int | None = None) -> np.ndarray:
+    """Star-shaped random polygons split into edges (closing edge included).
+
+    Polygon centre = one of 256 mixture centres + N(0, 2 deg); k ~ U{4..200}
+    vertices at sorted uniform angles; base radius log-normal (median 0.05
+    deg, sigma 1); vertex radius = base * U[0.5, 1].  The set is made of
+    independent chunks of about chunk_edges edges (generated in parallel for
+    large sets), each run until it holds its share; the total is at least
+    ``min_edges``.
+    """
+    n_chunks = max(1, -(-min_edges // chunk_edges))
+    share = -(-min_edges // n_chunks)
+    jobs = [(seed, c, n_chunks, share, n_centres, centre_sigma, batch_polygons) for c in range(n_chunks)]
+    if n_chunks == 1:
+        return _c4_chunk(jobs[0])
+    from multiprocessing import get_context
+    with get_context("fork").Pool(workers or _workers(n_chunks)) as pool:
+        parts = pool.map(_c4_chunk, jobs)
     return np.concatenate(parts, axis=0)
 
 

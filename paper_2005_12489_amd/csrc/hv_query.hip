@@ -499,6 +499,37 @@ __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *total, uint32_t *s
     return off + x - v;
 }
 
+// Region pixels whose centre lies within r, per axis, of the box
+// [x0, x1] x [y0, y1] (tile-local px), widened by kRangeEps; false if none.
+template <int RS>
+__device__ inline bool px_range(double x0, double x1, double y0, double y1, double r, double i0, double j0, int &ilo,
+                                int &ihi, int &jlo, int &jhi) {
+    const double flo_i = fmax(ceil(x0 - r - 0.5 - i0 - kRangeEps), 0.0);
+    const double fhi_i = fmin(floor(x1 + r - 0.5 - i0 + kRangeEps), RS - 1.0);
+    const double flo_j = fmax(ceil(y0 - r - 0.5 - j0 - kRangeEps), 0.0);
+    const double fhi_j = fmin(floor(y1 + r - 0.5 - j0 + kRangeEps), RS - 1.0);
+    if (!(flo_i <= fhi_i && flo_j <= fhi_j)) return false;
+    ilo = (int)flo_i;
+    ihi = (int)fhi_i;
+    jlo = (int)flo_j;
+    jhi = (int)fhi_j;
+    return true;
+}
+
+// True when every region pixel of the range is already lit.  Pixels are
+// only ever set, so a node or object whose whole range is lit can be
+// skipped without changing the mask.
+template <int W>
+__device__ inline bool range_lit(const uint32_t *mask, int ilo, int ihi, int jlo, int jhi) {
+    for (int jj = jlo; jj <= jhi; ++jj)
+        for (int w = ilo >> 5; w <= (ihi >> 5); ++w) {
+            const int c0 = max(ilo, 32 * w) - 32 * w, c1 = min(ihi, 32 * w + 31) - 32 * w;
+            const uint32_t want = (c1 == 31 ? 0xffffffffu : ((1u << (c1 + 1)) - 1u)) & ~((1u << c0) - 1u);
+            if ((mask[jj * W + w] & want) != want) return false;
+        }
+    return true;
+}
+
 __device__ inline int region_cells(uint32_t rg) {
     const int ilo = rg & 63, ihi = (rg >> 6) & 63, jlo = (rg >> 12) & 63, jhi = (rg >> 18) & 63;
     return (jhi - jlo + 1) * ((ihi >> 3) - (ilo >> 3) + 1);
@@ -613,10 +644,14 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         return all;
     };
 
+    // containment accepts keep a margin so that they never claim a pixel whose
+    // distance could round to just above r
+    const double racc = r - 1e-7, racc2 = racc * racc;
     bool done = false;
     for (;;) {
         const int sp = ctl[0];
         if (sp == 0) break;
+        bool accepted = false;
         const int lvl = (int)(stk[sp - 1] >> kLevelShift);
         // an inner step tests one child per thread; a leaf step OPL objects per thread
         const int per_step = lvl > 0 ? nthr / kFan : nthr * OPL / kLeaf;
@@ -629,10 +664,43 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
             __syncthreads();
             const int cl = lvl - 1;
             const int64_t child = (int64_t)node * kFan + c;
-            const bool hit = j < npop && child < ix.meta[kMaxLevels + cl] &&
-                             meets(ix.nodes[ix.meta[cl] + child], qx0, qx1, qy0, qy1);
-            const int pos = wave_alloc(&ctl[0], __ballot(hit), lane);
-            if (hit) stk[pos] = ((uint32_t)cl << kLevelShift) | (uint32_t)child;
+            bool push = false;
+            if (j < npop && child < ix.meta[kMaxLevels + cl]) {
+                const double4 nb = ix.nodes[ix.meta[cl] + child];
+                if (meets(nb, qx0, qx1, qy0, qy1)) {
+                    const double bx0 = nb.x * S - ox, bx1 = nb.z * S - ox;
+                    const double by0 = nb.y * S - oy, by1 = nb.w * S - oy;
+                    int ilo, ihi, jlo, jhi;
+                    push = px_range<RS>(bx0, bx1, by0, by1, r, i0, j0, ilo, ihi, jlo, jhi);
+                    if (push && racc > 0.0 && (bx1 - bx0) * (bx1 - bx0) + (by1 - by0) * (by1 - by0) <= 4.0 * racc2) {
+                        // containment accept: the node holds at least one object and
+                        // lies wholly within racc of these pixel centres, so they are
+                        // lit without looking at its objects
+                        for (int jj = jlo; jj <= jhi; ++jj) {
+                            const double cy = j0 + (double)jj + 0.5;
+                            const double dy = fmax(fabs(cy - by0), fabs(cy - by1));
+                            if (dy * dy > racc2) continue;
+                            uint64_t bits = 0;
+                            for (int ii = ilo; ii <= ihi; ++ii) {
+                                const double cx = i0 + (double)ii + 0.5;
+                                const double dx = fmax(fabs(cx - bx0), fabs(cx - bx1));
+                                if (dx * dx + dy * dy <= racc2) bits |= 1ull << ii;
+                            }
+#pragma unroll
+                            for (int wd = 0; wd < W; ++wd) {
+                                const uint32_t wb = (uint32_t)(bits >> (32 * wd));
+                                if (wb) {
+                                    atomicOr(&mask[jj * W + wd], wb);
+                                    accepted = true;
+                                }
+                            }
+                        }
+                    }
+                    if (push && range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
+                }
+            }
+            const int pos = wave_alloc(&ctl[0], __ballot(push), lane);
+            if (push) stk[pos] = ((uint32_t)cl << kLevelShift) | (uint32_t)child;
         } else {
             // issue all OPL loads first so that they are in flight together
             double4 ob[OPL];
@@ -673,7 +741,8 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     const double fhi_i = fmin(floor(fmax(ua, ub) + r - 0.5 - i0 + kRangeEps), RS - 1.0);
                     const double flo_j = fmax(ceil(fmin(va, vb) - r - 0.5 - j0 - kRangeEps), 0.0);
                     const double fhi_j = fmin(floor(fmax(va, vb) + r - 0.5 - j0 + kRangeEps), RS - 1.0);
-                    if (flo_i <= fhi_i && flo_j <= fhi_j) {
+                    if (flo_i <= fhi_i && flo_j <= fhi_j &&
+                        !range_lit<W>(mask, (int)flo_i, (int)fhi_i, (int)flo_j, (int)fhi_j)) {
                         keep = true;
                         rg = (uint32_t)flo_i | ((uint32_t)fhi_i << 6) | ((uint32_t)flo_j << 12) |
                              ((uint32_t)fhi_j << 18);
@@ -692,7 +761,15 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                 }
             }
         }
-        __syncthreads();
+        if (__syncthreads_or(accepted)) {
+            // accepts may have lit the whole region
+            bool full = true;
+            for (int k = tid; k < RS * W; k += nthr) full &= mask[k] == 0xffffffffu;
+            if (__syncthreads_and(full)) {
+                done = true;
+                break;
+            }
+        }
         if (ctl[1] > cap - nthr * OPL && drain()) {
             done = true;
             break;

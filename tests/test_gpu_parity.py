@@ -220,3 +220,35 @@ def test_invalid_coordinates_rejected(hv, torch):
         with pytest.raises(hv.HvError, match="non-finite|lon|lat") as e:
             hv.hv_index_build(t, hv.HV_POINTS)
         assert e.value.code == hv.HV_EINVAL
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_dense_low_zoom_accepts(hv, torch, kind):
+    """Tree nodes far smaller than a pixel (dense clusters at zooms 0-6):
+    containment accepts and skipping of fully lit ranges decide most pixels;
+    every mode must still equal the oracle."""
+    rng = np.random.default_rng(50 + kind)
+    n = 400_000
+    c = np.array([[12.0, 41.0], [-70.0, -20.0], [100.0, 30.0]])
+    k = rng.integers(0, 3, n)
+    a = c[k] + rng.normal(0, [[0.3], [1.5], [4.0]][0][0], (n, 2)) * np.array([1.0, 1.0])
+    a = np.clip(a, [-179.9, -84.9], [179.9, 84.9])
+    objs = a if kind == 0 else np.concatenate([a, np.clip(a + rng.normal(0, 0.01, (n, 2)), [-179.9, -84.9],
+                                                          [179.9, 84.9])], 1)
+    m = merc01(c)
+    tiles = [(0, 0, 0)]
+    for z in (2, 4, 6):
+        for q in m:
+            tiles.append((z, int(q[0] * 2 ** z), int(q[1] * 2 ** z)))
+    tiles = np.array(tiles)
+    log(f"dense low zoom kind={kind}")
+    h = build(hv, torch, objs, kind)
+    ix = oracle.OracleIndex(objs, kind)
+    for r in (0.5, 1.0, 2.5):
+        tri = ix.render(tiles, r)["tri"]
+        ref = render(hv, torch, h, tiles, r)
+        _assert_parity(ref, tri, f"dense kind={kind} r={r}")
+        for L in (dict(region=64, waves_per_wg=4, cand_cap=256), dict(region=0, block=16, waves_per_wg=2),
+                  dict(region=32, waves_per_wg=2, objs_per_lane=2, cand_cap=256)):
+            assert np.array_equal(render(hv, torch, h, tiles, r, launch=L), ref), (r, L)
+    hv.hv_free(h)
