@@ -12,6 +12,10 @@ Workloads (--workload):
                 zooms 0-18, radius 1-3 px.
   c4            >= 2e8 star-polygon edges; 4,096 mixed requests per launch at
                 zooms 2-20, widths 1-5 px.
+  c5            serving: the c2 and c3 indexes resident; Poisson arrivals at
+                1k-50k requests/s over both, zooms 0-20, mixed styles;
+                continuous batching on two streams against one launch per
+                request (20,000 requests or 10 s per rate).
 
 Reported beside the batched figure: per-request latency p50/p99 inside a
 batch (device completion stamps), the same requests as one plain
@@ -49,7 +53,9 @@ WORKLOADS = {
     "c2": dict(name="linestrings-10M-z6-all4096-w1", kind=1),
     "c3": dict(name="points-1e9-clustered-10000tiles-z0-18-r1-3", kind=0),
     "c4": dict(name="polygon-edges-2e8-4096mixed-z2-20-w1-5", kind=2),
+    "c5": dict(name="serving-linestrings-10M+points-1e9-poisson-1k-50k", kind=-1),
 }
+RATES = (1000.0, 2000.0, 5000.0, 10000.0, 20000.0, 50000.0)
 
 
 def make_workload(key: str, scale: float = 1.0):
@@ -133,6 +139,70 @@ def cpu_baseline(objs, kind, tiles, r, seconds: float):
                       f"{dt:.1f} s of CPU work on {threads} threads; index build untimed{note}"}
 
 
+def serve_bench(args, hv, torch):
+    """Serving sweep over request rates: continuous batching vs one launch per request."""
+    from paper_2005_12489_amd import serve
+    segs = hvgen.gen_c2_segments()
+    n3 = int(1_000_000_000 * args.scale)
+    pts = hvgen.gen_c3_points(n3)
+    hs = []
+    for objs, kind in ((segs, hv.HV_SEGMENTS), (pts, hv.HV_POINTS)):
+        d = torch.from_numpy(objs).cuda()
+        torch.cuda.synchronize()
+        hs.append(hv.hv_index_build(d, kind))
+        del d
+        torch.cuda.empty_cache()
+    levels = max(hv.hv_index_info(h)["levels"] for h in hs)
+    del pts
+    rows = []
+    for rate in RATES:
+        arr = hvgen.c5_arrivals(rate, c2_objects=segs)
+        reqs = hv.requests(np.where(arr["dataset"] == 0, hs[0], hs[1]).astype(np.uint64), arr["tiles"], arr["r"])
+        row = {"rate": rate, "requests": len(reqs)}
+        for mode, mb in (("batched", 4096), ("per_request", 1)):
+            ex = serve.GpuExecutor(reqs, streams=2, max_batch=mb, max_indexes=2, max_levels=levels)
+            warm = np.arange(min(64, len(reqs)))
+            serve.serve(np.zeros(len(warm)), serve.Scheduler(max_batch=mb), _Subset(ex, warm))
+            st = serve.serve(arr["t"], serve.Scheduler(max_batch=mb), ex)
+            ex.close()
+            row[mode] = {k: st[k] for k in ("tiles_per_s", "p50_ms", "p99_ms", "max_ms", "batches", "mean_batch")}
+        print(json.dumps({"serving_rate": rate, **row}), file=sys.stderr, flush=True)
+        rows.append(row)
+    for h in hs:
+        hv.hv_free(h)
+    top = rows[-1]
+    rec = {
+        "metric": METRIC, "value": top["batched"]["tiles_per_s"], "unit": "tiles/s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c5"]["name"], "n_segments": int(segs.shape[0]), "n_points": n3,
+                   "rates_per_s": list(RATES), "streams": 2, "max_batch": 4096},
+        "serving": rows,
+        "note": "value = served tiles/s at the highest offered rate; latency = completion (masks on the "
+                "host) - scheduled arrival",
+    }
+    print(json.dumps(rec))
+
+
+class _Subset:
+    """Serves a few requests of an executor once (warm-up)."""
+
+    def __init__(self, ex, ids):
+        self.ex, self.ids = ex, ids
+
+    def idle_lane(self):
+        return self.ex.idle_lane()
+
+    def launch(self, lane, ids):
+        self.ex.launch(lane, self.ids[np.asarray(ids)])
+
+    def poll(self):
+        out = []
+        for ids, t in self.ex.poll():
+            out.append((np.searchsorted(self.ids, ids), t))
+        return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +236,8 @@ def main():
     from paper_2005_12489_amd import hv
 
     torch.cuda.set_device(0)
+    if args.workload == "c5":
+        return serve_bench(args, hv, torch)
     wl = WORKLOADS[args.workload]
     objs, tiles, rr, cfg = make_workload(args.workload, args.scale)
     n = len(tiles)

@@ -1,0 +1,55 @@
+"""Serving on the GPU: Poisson arrivals over two resident indexes, admitted
+and batched as they arrive on two streams.  Each served mask must equal the
+same request rendered alone, and the oracle."""
+import numpy as np
+import pytest
+
+import hvgen
+import oracle
+from gpu_common import build, log
+from helpers import parity, unpack_masks
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "needs a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def hv():
+    from paper_2005_12489_amd import hv as m
+    return m
+
+
+def test_served_equals_alone_and_oracle(hv, torch):
+    from paper_2005_12489_amd import serve
+    segs = hvgen.gen_c2_segments(n_segments=300_000)
+    pts = hvgen.gen_c3_points(300_000)
+    log("serve: build two indexes")
+    h2, h3 = build(hv, torch, segs, hv.HV_SEGMENTS), build(hv, torch, pts, hv.HV_POINTS)
+    arr = hvgen.c5_arrivals(20000.0, c2_objects=segs, max_requests=3000, zmax=14)
+    ds = arr["dataset"]
+    reqs = hv.requests(np.where(ds == 0, h2, h3).astype(np.uint64), arr["tiles"], arr["r"])
+    ex = serve.GpuExecutor(reqs, streams=2, max_batch=512, max_indexes=2, max_levels=12, keep_masks=True)
+    log("serve: 3000 requests at 20k req/s")
+    st = serve.serve(arr["t"], serve.Scheduler(max_batch=512), ex)
+    ex.close()
+    log(f"serve: batches={st['batches']} mean={st['mean_batch']:.1f} p50={st['p50_ms']:.3f} ms "
+        f"p99={st['p99_ms']:.3f} ms tiles/s={st['tiles_per_s']:.0f}")
+    assert st["batches"] > 1 and np.all(np.isfinite(st["latency_s"]))
+    served = unpack_masks(ex.masks)
+    alone = torch.empty((1, 8192), dtype=torch.uint8, device="cuda")
+    for k in range(len(reqs)):
+        hv.hv_render_batch(reqs[k:k + 1], alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(unpack_masks(alone.cpu().numpy())[0], served[k]), k
+    for d, objs, kind in ((0, segs, oracle.SEGMENTS), (1, pts, oracle.POINTS)):
+        sel = np.nonzero(ds == d)[0][:150]
+        tri = oracle.OracleIndex(objs, kind).render(arr["tiles"][sel], arr["r"][sel])["tri"]
+        assert parity(served[sel], tri)[0] == 0, d
+    hv.hv_free(h2)
+    hv.hv_free(h3)
