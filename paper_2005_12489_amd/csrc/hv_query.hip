@@ -565,8 +565,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         ctl[1] = 0;
     }
     __syncthreads();
-    {
-        const int fcount = fmeta[2 * t], flevel = fmeta[2 * t + 1];
+    const int fcount = fmeta[2 * t], flevel = fmeta[2 * t + 1];
+    // pushes the frontier nodes that meet the region
+    auto push_frontier = [&]() {
         for (int base = 0; base < fcount; base += nthr) {
             bool hit = false;
             uint32_t node = 0;
@@ -577,8 +578,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
             const int pos = wave_alloc(&ctl[0], __ballot(hit), lane);
             if (hit) stk[pos] = ((uint32_t)flevel << kLevelShift) | node;
         }
-    }
-    __syncthreads();
+        __syncthreads();
+    };
+    push_frontier();
 
     // Tests every queued object against its pixels; returns true once the
     // whole region is lit.
@@ -644,13 +646,27 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         return all;
     };
 
-    // containment accepts keep a margin so that they never claim a pixel whose
+    // edge accepts keep a margin so that they never claim a pixel whose
     // distance could round to just above r
     const double racc = r - 1e-7, racc2 = racc * racc;
+    // Two walks.  The first (accept pass) descends only until nodes are small
+    // enough for their edge accepts to cover the pixels around them, makes
+    // those accepts and reads no objects; it skips subtrees whose leaves are
+    // unlikely to be that small.  In dense data it lights most pixels, so
+    // that the second, full walk finds most ranges lit and reads few objects.
+    // A frontier made of leaves takes the full walk only.
+    bool accept_pass = racc > 0.0 && flevel > 0;
     bool done = false;
     for (;;) {
         const int sp = ctl[0];
-        if (sp == 0) break;
+        if (sp == 0) {
+            if (!accept_pass) break;
+            accept_pass = false;
+            // every wave has read the empty stack before any pushes to it
+            __syncthreads();
+            push_frontier();
+            continue;
+        }
         bool accepted = false;
         const int lvl = (int)(stk[sp - 1] >> kLevelShift);
         // an inner step tests one child per thread; a leaf step OPL objects per thread
@@ -672,19 +688,29 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     const double by0 = nb.y * S - oy, by1 = nb.w * S - oy;
                     int ilo, ihi, jlo, jhi;
                     push = px_range<RS>(bx0, bx1, by0, by1, r, i0, j0, ilo, ihi, jlo, jhi);
-                    if (push && racc > 0.0 && (bx1 - bx0) * (bx1 - bx0) + (by1 - by0) * (by1 - by0) <= 4.0 * racc2) {
-                        // containment accept: the node holds at least one object and
-                        // lies wholly within racc of these pixel centres, so they are
-                        // lit without looking at its objects
+                    const double bw = bx1 - bx0, bh = by1 - by0;
+                    const double diag2 = bw * bw + bh * bh;
+                    const bool small = racc > 0.0 && bw <= 2.0 * racc && bh <= 2.0 * racc;
+                    if (push && small) {
+                        // Edge accept.  A node box is the exact bounding box of
+                        // its objects' coordinates (points, segment endpoints),
+                        // so each of its four edges holds a point of some object.
+                        // A pixel centre within racc of both ends of one edge is
+                        // within racc of that point, hence lit, without looking
+                        // at the objects.
                         for (int jj = jlo; jj <= jhi; ++jj) {
                             const double cy = j0 + (double)jj + 0.5;
-                            const double dy = fmax(fabs(cy - by0), fabs(cy - by1));
-                            if (dy * dy > racc2) continue;
+                            const double ey0 = fabs(cy - by0), ey1 = fabs(cy - by1);
+                            const double dyn = fmin(ey0, ey1), dyf = fmax(ey0, ey1);
+                            if (dyn * dyn > racc2) continue;
                             uint64_t bits = 0;
                             for (int ii = ilo; ii <= ihi; ++ii) {
                                 const double cx = i0 + (double)ii + 0.5;
-                                const double dx = fmax(fabs(cx - bx0), fabs(cx - bx1));
-                                if (dx * dx + dy * dy <= racc2) bits |= 1ull << ii;
+                                const double ex0 = fabs(cx - bx0), ex1 = fabs(cx - bx1);
+                                const double dxn = fmin(ex0, ex1), dxf = fmax(ex0, ex1);
+                                // nearer vertical edge, or nearer horizontal edge
+                                if (dxn * dxn + dyf * dyf <= racc2 || dxf * dxf + dyn * dyn <= racc2)
+                                    bits |= 1ull << ii;
                             }
 #pragma unroll
                             for (int wd = 0; wd < W; ++wd) {
@@ -697,6 +723,12 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         }
                     }
                     if (push && range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
+                    // The accept pass stops at leaves and at nodes no wider than
+                    // racc: nodes of that size, spread over an area, light every
+                    // pixel centre of it.  It enters a larger node only if its
+                    // leaves, at about 4^-level of its size, could be small.
+                    if (accept_pass && push && (diag2 <= racc2 || cl == 0 || diag2 > ldexp(16.0 * racc2, 4 * cl)))
+                        push = false;
                 }
             }
             const int pos = wave_alloc(&ctl[0], __ballot(push), lane);

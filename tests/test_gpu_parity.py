@@ -252,3 +252,43 @@ def test_dense_low_zoom_accepts(hv, torch, kind):
                   dict(region=32, waves_per_wg=2, objs_per_lane=2, cand_cap=256)):
             assert np.array_equal(render(hv, torch, h, tiles, r, launch=L), ref), (r, L)
     hv.hv_free(h)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_edge_accepts_small_clusters(hv, torch, kind):
+    """Clusters whose bounding boxes are about as wide as the radius, so that
+    edge accepts (a pixel within r of both ends of one side of a node box)
+    decide many pixels at the very edge of what they may claim."""
+    rng = np.random.default_rng(60 + kind)
+    z0 = 5
+    nclu = 3000
+    per = 16 * rng.integers(1, 17, nclu)
+    clon = rng.uniform(0.0, 45.0, nclu)
+    clat = rng.uniform(22.0, 55.0, nclu)
+    deg_px = 360.0 / (256 * 2 ** z0)
+    ex = rng.uniform(0.05, 6.0, nclu) * deg_px
+    ey = rng.uniform(0.05, 6.0, nclu) * deg_px * np.cos(np.radians(clat))
+    idx = np.repeat(np.arange(nclu), per)
+    m = len(idx)
+    lon = clon[idx] + (rng.random(m) - 0.5) * ex[idx]
+    lat = clat[idx] + (rng.random(m) - 0.5) * ey[idx]
+    if kind == 0:
+        objs = np.stack([lon, lat], 1)
+    else:
+        lon2 = clon[idx] + (rng.random(m) - 0.5) * ex[idx]
+        lat2 = clat[idx] + (rng.random(m) - 0.5) * ey[idx]
+        objs = np.stack([lon, lat, lon2, lat2], 1)
+    anchors = merc01(np.stack([clon[:40], clat[:40]], 1))
+    tiles = sorted({(z, int(q[0] * 2 ** z), int(q[1] * 2 ** z)) for z in range(3, 9) for q in anchors})
+    tiles = np.array(tiles)
+    log(f"edge accepts kind={kind} objects={m} tiles={len(tiles)}")
+    h = build(hv, torch, objs, kind)
+    ix = oracle.OracleIndex(objs, kind)
+    for r in (0.5, 1.0, 1.7, 3.0):
+        tri = ix.render(tiles, r)["tri"]
+        ref = render(hv, torch, h, tiles, r)
+        _assert_parity(ref, tri, f"edge accepts kind={kind} r={r}")
+        for L in (dict(region=64, waves_per_wg=4, cand_cap=256), dict(region=0, block=16, waves_per_wg=2),
+                  dict(region=32, waves_per_wg=2, objs_per_lane=2, cand_cap=256)):
+            assert np.array_equal(render(hv, torch, h, tiles, r, launch=L), ref), (r, L)
+    hv.hv_free(h)
