@@ -58,6 +58,19 @@ WORKLOADS = {
 RATES = (1000.0, 2000.0, 5000.0, 10000.0, 20000.0, 50000.0)
 
 
+_T0 = time.perf_counter()
+
+
+def stage(msg: str) -> None:
+    """Progress line on stderr (long runs must keep writing)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def _gen_progress(done: int, total: int) -> None:
+    if done == total or done % 10 == 0:
+        stage(f"generated chunk {done}/{total}")
+
+
 def make_workload(key: str, scale: float = 1.0):
     """(objects, tiles (n,3), r (n,), config dict)."""
     if key == "c1":
@@ -73,7 +86,7 @@ def make_workload(key: str, scale: float = 1.0):
         return objs, tiles, np.full(len(tiles), r), cfg
     if key == "c3":
         n = int(1_000_000_000 * scale)
-        objs = hvgen.gen_c3_points(n)
+        objs = hvgen.gen_c3_points(n, progress=_gen_progress)
         tiles, r = hvgen.c3_requests(10_000)
         cfg = {"n_points": n, "zooms": "0-18", "tiles": int(len(tiles)), "r_px": "U[1,3]"}
         return objs, tiles, r, cfg
@@ -104,29 +117,32 @@ def cpu_baseline(objs, kind, tiles, r, seconds: float):
     threads = oracle.default_threads()
     note = ""
     if objs.shape[0] > 50_000_000:
-        # keep the objects whose first vertex lies within one zoom-8 cell of a
-        # sampled request (a cell is 1.4 degrees wide)
-        sample = order[:64]
+        # A host index over the whole set is out of reach here, so the sample
+        # is drawn from the requests at zoom >= 8 and the oracle indexes the
+        # objects whose first vertex lies within one zoom-8 cell (1.4 degrees)
+        # of one of them.
+        deep = order[tiles[order, 0] >= 8]
+        sample = deep[:64]
+        stage("oracle baseline: projecting the objects to pick the sample's")
         X, Y = oracle.project(objs[:, :2])
         cell = np.minimum((Y * 256).astype(np.int32), 255) * 256 + np.minimum((X * 256).astype(np.int32), 255)
         del X, Y
         need = set()
         for t in sample:
             z, x, y = (int(v) for v in tiles[t])
-            if z >= 8:
-                x0 = x1 = x >> (z - 8)
-                y0 = y1 = y >> (z - 8)
-            else:
-                x0, x1 = x << (8 - z), ((x + 1) << (8 - z)) - 1
-                y0, y1 = y << (8 - z), ((y + 1) << (8 - z)) - 1
-            for cy in range(max(0, y0 - 1), min(255, y1 + 1) + 1):
-                for cx in range(max(0, x0 - 1), min(255, x1 + 1) + 1):
+            x0 = x >> (z - 8)
+            y0 = y >> (z - 8)
+            for cy in range(max(0, y0 - 1), min(255, y0 + 1) + 1):
+                for cx in range(max(0, x0 - 1), min(255, x0 + 1) + 1):
                     need.add(cy * 256 + cx)
+        stage("oracle baseline: selecting")
         objs = objs[np.isin(cell, np.fromiter(need, dtype=np.int32))]
         order = sample
-        note = (f"; index over the {objs.shape[0]} objects whose first vertex lies within one zoom-8 "
-                "cell of the 64 sampled requests")
+        note = (f"; {len(sample)} requests drawn among those at zoom >= 8 only, and an index over the "
+                f"{objs.shape[0]} objects whose first vertex lies within one zoom-8 cell of them")
+    stage(f"oracle baseline: building the oracle index over {objs.shape[0]} objects")
     ix = oracle.OracleIndex(objs, kind)
+    stage("oracle baseline: rendering")
     done, t0 = 0, time.perf_counter()
     chunk = max(threads, 8)
     while done < len(order) and time.perf_counter() - t0 < seconds:
@@ -144,7 +160,7 @@ def serve_bench(args, hv, torch):
     from paper_2005_12489_amd import serve
     segs = hvgen.gen_c2_segments()
     n3 = int(1_000_000_000 * args.scale)
-    pts = hvgen.gen_c3_points(n3)
+    pts = hvgen.gen_c3_points(n3, progress=_gen_progress)
     hs = []
     for objs, kind in ((segs, hv.HV_SEGMENTS), (pts, hv.HV_POINTS)):
         d = torch.from_numpy(objs).cuda()
@@ -152,6 +168,7 @@ def serve_bench(args, hv, torch):
         hs.append(hv.hv_index_build(d, kind))
         del d
         torch.cuda.empty_cache()
+        stage(f"index built over {objs.shape[0]} objects")
     levels = max(hv.hv_index_info(h)["levels"] for h in hs)
     del pts
     rows = []
@@ -166,6 +183,7 @@ def serve_bench(args, hv, torch):
             st = serve.serve(arr["t"], serve.Scheduler(max_batch=mb), ex)
             ex.close()
             row[mode] = {k: st[k] for k in ("tiles_per_s", "p50_ms", "p99_ms", "max_ms", "batches", "mean_batch")}
+            stage(f"rate {rate:g}/s {mode}: {st['tiles_per_s']:.0f} tiles/s p99 {st['p99_ms']:.2f} ms")
         print(json.dumps({"serving_rate": rate, **row}), file=sys.stderr, flush=True)
         rows.append(row)
     for h in hs:
@@ -239,8 +257,10 @@ def main():
     if args.workload == "c5":
         return serve_bench(args, hv, torch)
     wl = WORKLOADS[args.workload]
+    stage(f"workload {args.workload}: generating")
     objs, tiles, rr, cfg = make_workload(args.workload, args.scale)
     n = len(tiles)
+    stage(f"{objs.shape[0]} objects, {n} requests")
 
     d_objs = torch.from_numpy(objs).cuda()
     torch.cuda.synchronize()
@@ -250,11 +270,14 @@ def main():
     torch.cuda.empty_cache()
     reqs = hv.requests(h, tiles, rr)
     out = torch.empty((n, hv.HV_MASK_BYTES), dtype=torch.uint8, device="cuda")
+    stage(f"index built: {info['levels']} levels, {info['build_ms']:.1f} ms")
 
     launch = json.loads(args.launch) if args.launch else None
     tuned_ms = None
     if launch is None and not args.no_autotune:
-        launch, tuned_ms = hv.hv_autotune(reqs, out)
+        tune = np.arange(n) if n <= 1024 else np.arange(1024) * n // 1024
+        launch, tuned_ms = hv.hv_autotune(reqs[tune], out[:len(tune)])
+        stage(f"autotuned: {launch}")
 
     # batched: one graph launch per step
     batcher = hv.hv_batcher_create(n, max_indexes=1, max_levels=info["levels"], launch=launch)
@@ -275,6 +298,7 @@ def main():
     wall = t1 - t0
     value = n * args.steps / wall
     kernel_ms = float(np.mean(step_ms))
+    stage(f"timed {args.steps} steps: {wall / args.steps * 1e3:.3f} ms/step")
 
     # the same requests as one plain (not graph-captured) call
     for _ in range(2):
@@ -321,6 +345,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        stage("oracle baseline")
         cpu = cpu_baseline(objs, wl["kind"], tiles, rr, args.cpu_seconds)
 
     hv.hv_free(h)

@@ -178,37 +178,28 @@ def _workers(jobs: int) -> int:
     return max(1, min(jobs, 16, len(os.sched_getaffinity(0))))
 
 
-def _c3_fill(args):
-    shm_name, n, chunk, chunk_size, seed, n_chunks = args
-    from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(name=shm_name)
-    try:
-        out = np.ndarray((n, 2), dtype=np.float64, buffer=shm.buf)
-        lo = chunk * chunk_size
-        m = min(chunk_size, n - lo)
-        out[lo:lo + m] = gen_c3_chunk(chunk, chunk_size, seed, n_chunks)[:m]
-        del out
-    finally:
-        shm.close()
-    return chunk
-
-
-def gen_c3_points(n: int, seed: int = 3, chunk_size: int = 10_000_000, workers: int | None = None) -> np.ndarray:
-    """The clustered point set, chunk by chunk (chunks are independent, so
-    large sets are generated by parallel processes into shared memory)."""
+def gen_c3_points(n: int, seed: int = 3, chunk_size: int = 10_000_000, workers: int | None = None,
+                  progress=None) -> np.ndarray:
+    """The clustered point set, chunk by chunk.  Chunks are independent, so
+    large sets are filled by a thread pool (numpy's generators and array
+    arithmetic release the GIL) straight into one array; ``progress(done,
+    total)`` is called as chunks finish."""
     n_chunks = max(1, -(-n // chunk_size))
     spawn = max(100, n_chunks)
     if n_chunks == 1:
         return gen_c3_chunk(0, chunk_size, seed, spawn)[:n].copy()
-    from multiprocessing import get_context, shared_memory
-    shm = shared_memory.SharedMemory(create=True, size=n * 16)
-    try:
-        with get_context("fork").Pool(workers or _workers(n_chunks)) as pool:
-            pool.map(_c3_fill, [(shm.name, n, c, chunk_size, seed, spawn) for c in range(n_chunks)])
-        out = np.ndarray((n, 2), dtype=np.float64, buffer=shm.buf).copy()
-    finally:
-        shm.close()
-        shm.unlink()
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty((n, 2), dtype=np.float64)
+
+    def fill(chunk):
+        lo = chunk * chunk_size
+        m = min(chunk_size, n - lo)
+        out[lo:lo + m] = gen_c3_chunk(chunk, chunk_size, seed, spawn)[:m]
+
+    with ThreadPoolExecutor(workers or _workers(n_chunks)) as ex:
+        for k, _ in enumerate(ex.map(fill, range(n_chunks))):
+            if progress:
+                progress(k + 1, n_chunks)
     return out
 
 

@@ -214,7 +214,10 @@ int hv_batcher_latency(hv_batcher *b, double *latency_us, int64_t n);
 void hv_batcher_free(hv_batcher *b);
 
 /* Time a set of launch shapes on a sample batch and return the fastest in
- * *best (and its time per launch in *best_ms, may be NULL).  The result is
+ * *best (and its time per launch in *best_ms, may be NULL).  Each shape
+ * runs first on 16, then 128 evenly spread requests of the sample, then on
+ * all of it, and is dropped once a part takes more than twice the best
+ * time seen on that part.  The result is
  * also cached under the sample's class -- dominant kind, zoom band (z / 4)
  * and radius band (r <= 1, <= 2, <= 4, > 4) -- which hv_render_batch with
  * launch == NULL then uses for batches of that class.  scratch_masks:

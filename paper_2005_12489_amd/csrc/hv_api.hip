@@ -455,12 +455,24 @@ int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out) {
 int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_launch *best, double *best_ms) {
     if (!best) return fail(HV_EINVAL, "best is NULL");
     if (n <= 0) return fail(HV_EINVAL, "the sample is empty");
-    BatchPlan p;
-    int rc = plan_batch(sample, n, &p);
-    if (rc) return rc;
+    // Candidates are timed on growing, evenly spread parts of the sample (16
+    // requests, 128, then all of it) and dropped as soon as one part takes
+    // more than twice the best time seen on it, so that a shape that is very
+    // slow on this kind of batch costs one short run, not a full one.
+    constexpr int kStages = 3;
+    const int64_t sizes[kStages] = {std::min<int64_t>(n, 16), std::min<int64_t>(n, 128), n};
+    BatchPlan plans[kStages];
+    for (int st = 0; st < kStages; ++st) {
+        std::vector<hv_request> part((size_t)sizes[st]);
+        for (int64_t i = 0; i < sizes[st]; ++i) part[(size_t)i] = sample[i * n / sizes[st]];
+        int rc = plan_batch(part.data(), sizes[st], &plans[st]);
+        if (rc) return rc;
+    }
+    const BatchPlan &p = plans[kStages - 1];
+    int rc = HV_OK;
     if ((rc = validate_out(scratch_masks))) return rc;
     // candidate shapes: region mode (side, waves, objects per lane, queue)
-    // and one wave per block (side, waves, stage capacity)
+    // and one wave per block (side, waves, stage capacity); the default first
     static const hv_launch cands[] = {
         {0, 64, 1, 0, 32, 1},  {0, 128, 1, 0, 32, 2}, {0, 128, 2, 0, 32, 1}, {0, 256, 2, 0, 32, 2},
         {0, 256, 4, 0, 32, 1}, {0, 128, 2, 0, 64, 1}, {0, 256, 2, 0, 64, 2}, {0, 256, 4, 0, 64, 1},
@@ -471,27 +483,37 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_status(e, "hv_autotune");
-    double best_t = 1e300;
+    double stage_best[kStages] = {1e300, 1e300, 1e300};
     int best_k = -1;
-    for (int k = 0; k < (int)(sizeof(cands) / sizeof(cands[0])); ++k) {
+    for (int k = 0; k < (int)(sizeof(cands) / sizeof(cands[0])) && rc == HV_OK && e == hipSuccess; ++k) {
         hv::LaunchShape shape;
         if (resolve_shape(&cands[k], p.max_levels, &shape)) continue;  // does not fit this batch
-        float ms_min = 1e30f;
-        for (int rep = 0; rep < 4; ++rep) {
-            if ((e = hipEventRecord(e0, t_stream)) != hipSuccess) break;
-            rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, scratch_masks,
-                           shape, "hv_autotune");
-            if (rc) break;
-            if ((e = hipEventRecord(e1, t_stream)) != hipSuccess) break;
-            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-            float ms = 0;
-            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-            if (rep > 0 && ms < ms_min) ms_min = ms;  // the first run warms up
-        }
-        if (rc || e != hipSuccess) break;
-        if (ms_min < best_t) {
-            best_t = ms_min;
-            best_k = k;
+        for (int st = 0; st < kStages; ++st) {
+            if (st < kStages - 1 && sizes[st] == sizes[st + 1]) continue;
+            const BatchPlan &q = plans[st];
+            const int reps = st == kStages - 1 ? 4 : 2;
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < reps; ++rep) {
+                if ((e = hipEventRecord(e0, t_stream)) != hipSuccess) break;
+                rc = run_batch(q.table.data(), (int)q.table.size(), q.max_levels, q.reqs.data(), sizes[st],
+                               scratch_masks, shape, "hv_autotune");
+                if (rc) break;
+                if ((e = hipEventRecord(e1, t_stream)) != hipSuccess) break;
+                if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+                float ms = 0;
+                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+                if (rep > 0 && ms < ms_min) ms_min = ms;  // the first run warms up
+                if (rep == 0 && ms > 2.0 * stage_best[st]) {
+                    ms_min = ms;  // far behind already: no need to repeat
+                    break;
+                }
+            }
+            if (rc || e != hipSuccess) break;
+            if (ms_min > 2.0 * stage_best[st]) break;
+            if (ms_min < stage_best[st]) {
+                stage_best[st] = ms_min;
+                if (st == kStages - 1) best_k = k;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -500,7 +522,7 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     if (e != hipSuccess) return hip_status(e, "hv_autotune");
     if (best_k < 0) return fail(HV_EINVAL, "no candidate shape fits this batch");
     *best = cands[best_k];
-    if (best_ms) *best_ms = best_t;
+    if (best_ms) *best_ms = stage_best[kStages - 1];
     const TuneKey key = batch_key(sample, n);
     std::lock_guard<std::mutex> g(g_tune_mu);
     bool found = false;
