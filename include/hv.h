@@ -228,6 +228,17 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
  * if that class has not been tuned. */
 int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
 
+/* Kernel timing for roofline figures.  Renders the batch reps times, as
+ * hv_render_batch would (same arguments; launch NULL takes the tuned shape
+ * or the default), each time recording HIP events on the calling thread's
+ * stream before the tile-frontier kernel, between it and the query kernel,
+ * and after the query kernel.  ms (host, 2 entries) receives the mean
+ * duration in milliseconds of the frontier kernel (ms[0]) and of the query
+ * kernel (ms[1]).  Synchronous.  HV_EINVAL for an empty batch, reps outside
+ * [1, 100000] or ms NULL, before any device call. */
+int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
+                    double *ms);
+
 #ifdef __cplusplus
 }
 #endif

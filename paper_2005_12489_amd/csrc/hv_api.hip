@@ -146,7 +146,7 @@ thread_local HostStage t_stage;
 // Copies the staged workspace to a fresh stream-ordered device allocation
 // and launches the query; the allocation is released in stream order.
 int run_batch(const hv::DevIndex *ixs, int n_ix, int max_levels, const hv::DevReq *reqs, int64_t n_req,
-              uint8_t *out, const hv::LaunchShape &shape, const char *who) {
+              uint8_t *out, const hv::LaunchShape &shape, const char *who, hipEvent_t *marks = nullptr) {
     const hv::Workspace w = hv::workspace_layout(n_req, n_ix);
     hipError_t e = t_stage.acquire(w.staged_bytes());
     if (e != hipSuccess) return hip_status(e, who);
@@ -158,7 +158,7 @@ int run_batch(const hv::DevIndex *ixs, int n_ix, int max_levels, const hv::DevRe
     if (e == hipSuccess) e = hipEventRecord(t_stage.ev, t_stream);
     if (e == hipSuccess) {
         t_stage.pending = true;
-        e = hv::launch_query(w, dws, max_levels, shape, t_stream);
+        e = hv::launch_query(w, dws, max_levels, shape, t_stream, marks);
     }
     const hipError_t ef = hipFreeAsync(dws, t_stream);
     if (e != hipSuccess) return hip_status(e, who);
@@ -440,6 +440,44 @@ int hv_render_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_masks, shape,
                    "hv_render_batch");
     if (rc) return rc;
+    t_err.clear();
+    return HV_OK;
+}
+
+int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
+                    double *ms) {
+    if (!ms) return fail(HV_EINVAL, "ms is NULL");
+    if (reps < 1 || reps > 100000) return fail(HV_EINVAL, "reps must be in [1, 100000]");
+    if (n <= 0) return fail(HV_EINVAL, "the batch is empty");
+    BatchPlan p;
+    int rc = plan_batch(reqs, n, &p);
+    if (rc) return rc;
+    hv_launch tuned;
+    if (!launch && tuned_for(reqs, n, &tuned)) launch = &tuned;
+    hv::LaunchShape shape;
+    if ((rc = resolve_shape(launch, p.max_levels, &shape))) return rc;
+    if ((rc = validate_out(out_masks))) return rc;
+    hipEvent_t m[3] = {nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&m[k]);
+    double sum[2] = {0.0, 0.0};
+    for (int rep = 0; rep < reps && e == hipSuccess && rc == HV_OK; ++rep) {
+        rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_masks, shape,
+                       "hv_time_kernels", m);
+        if (rc) break;
+        if ((e = hipEventSynchronize(m[2])) != hipSuccess) break;
+        float a = 0, b = 0;
+        if ((e = hipEventElapsedTime(&a, m[0], m[1])) != hipSuccess) break;
+        if ((e = hipEventElapsedTime(&b, m[1], m[2])) != hipSuccess) break;
+        sum[0] += a;
+        sum[1] += b;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (m[k]) (void)hipEventDestroy(m[k]);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_status(e, "hv_time_kernels");
+    ms[0] = sum[0] / reps;
+    ms[1] = sum[1] / reps;
     t_err.clear();
     return HV_OK;
 }

@@ -78,7 +78,7 @@ struct BatchHeader {
     int64_t n_req;      // live requests
     uint8_t *out;       // masks: request k at out + k * 8192
     int32_t counter;    // tiles appended to the compacted list (0 when staged)
-    int32_t pad;
+    int32_t ecounter;   // tiles with no data within r, listed for zero-filling (0 when staged)
     uint64_t t_start;   // wall clock when the batch started on the device
 };
 
@@ -90,6 +90,7 @@ struct DevBatch {
     uint32_t *frontier;  // per request: up to 256 frontier nodes
     int32_t *fmeta;      // per request: frontier size, frontier level
     uint32_t *list;      // compacted list of requests with data nearby
+    uint32_t *elist;     // requests whose tile has no data within r
     uint32_t *done;      // per request: parts finished
     uint64_t *ts;        // per request: wall clock at completion
 };
@@ -99,7 +100,7 @@ struct DevBatch {
 // from the host; the rest is written by the kernels.
 struct Workspace {
     int64_t n_req;
-    size_t hdr_off, table_off, req_off, frontier_off, fmeta_off, list_off, done_off, ts_off, total;
+    size_t hdr_off, table_off, req_off, frontier_off, fmeta_off, list_off, elist_off, done_off, ts_off, total;
     size_t staged_bytes() const { return frontier_off; }
 };
 Workspace workspace_layout(int64_t n_req, int n_ix);
@@ -111,9 +112,11 @@ void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq 
 DevBatch device_batch(const Workspace &w, unsigned char *dws);
 
 // Launches the tile-frontier and query kernels for a staged workspace `dws`
-// (device) on `stream`; the grids cover w.n_req requests.
+// (device) on `stream`; the grids cover w.n_req requests.  With `marks`
+// (three events, or NULL) it records marks[0] before the frontier kernel,
+// marks[1] between the two and marks[2] after the query kernel.
 hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,
-                        hipStream_t stream);
+                        hipStream_t stream, hipEvent_t *marks = nullptr);
 
 // Workgroups that fill the current device for a shape (occupancy x CUs).
 int persistent_grid(const LaunchShape &s, int max_levels);

@@ -7,9 +7,9 @@
 //  1. k_tile_frontier -- one wavefront per request walks the tree breadth-
 //     first with the tile's box grown by r and keeps the deepest level at
 //     which at most 256 nodes meet it.  A tile whose frontier is empty misses
-//     all data: it writes its zero mask here and takes no further work
-//     (Sec. 4.1: tiles outside the data's bounds make no task).  The others
-//     are appended to a compacted work list.
+//     all data and takes no further work (Sec. 4.1: tiles outside the data's
+//     bounds make no task); it goes to a list of tiles whose masks the query
+//     kernel zero-fills.  The others are appended to a compacted work list.
 //  2. k_query -- a persistent grid (as many workgroups as the GPU holds at
 //     once) strides over the (tile, pixel block) items of that list, one
 //     wavefront per block (8x8, 16x16 or 32x32: 1, 4 or 16 pixels per lane),
@@ -72,7 +72,6 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
     if (blockIdx.x == 0 && threadIdx.x == 0) B.hdr->t_start = wall_clock64();
     const int64_t t = (int64_t)blockIdx.x * 4 + wv;
     if (t >= B.hdr->n_req) return;
-    uint8_t *const out = B.hdr->out;
     const DevReq rq = B.reqs[t];
     const DevIndex ix = B.ixs[rq.index];
     const double iS = ldexp(1.0, -8 - rq.z);
@@ -114,10 +113,9 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
         --lvl;
     }
     if (ncur == 0) {
-        // no data within r of the tile: the whole mask is zero
-        uint4 *m4 = reinterpret_cast<uint4 *>(out + t * (int64_t)HV_MASK_BYTES);
-        for (int k = lane; k < HV_MASK_BYTES / 16; k += 64) m4[k] = make_uint4(0, 0, 0, 0);
-        if (lane == 0) B.ts[t] = wall_clock64();
+        // no data within r of the tile: its mask is all zero, written by the
+        // query kernel
+        if (lane == 0) B.elist[atomicAdd(&B.hdr->ecounter, 1)] = (uint32_t)t;
         return;
     }
     for (int k = lane; k < ncur; k += 64) B.frontier[t * kFrontier + k] = cur[k];
@@ -126,6 +124,19 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
         B.fmeta[2 * t + 1] = lvl;
         B.done[t] = 0;
         B.list[atomicAdd(&B.hdr->counter, 1)] = (uint32_t)t;
+    }
+}
+
+// Writes the zero masks of the requests whose tile has no data within r
+// (listed by the tile-frontier kernel); workgroups take them in turn.
+__device__ inline void zero_empty_tiles(const DevBatch &B, uint8_t *out) {
+    const int ne = B.hdr->ecounter;
+    for (int e = blockIdx.x; e < ne; e += gridDim.x) {
+        const int64_t t = B.elist[e];
+        uint4 *m4 = reinterpret_cast<uint4 *>(out + t * (int64_t)HV_MASK_BYTES);
+        for (int k = threadIdx.x; k < HV_MASK_BYTES / 16; k += blockDim.x) m4[k] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        if (threadIdx.x == 0) B.ts[t] = wall_clock64();
     }
 }
 
@@ -421,6 +432,7 @@ __global__ __launch_bounds__(256) void k_query(DevBatch B, int cap, int max_leve
     // a workgroup's waves take consecutive blocks of one tile
     const int per_wg = (BPT + wpb - 1) / wpb;
     uint8_t *const out = B.hdr->out;
+    zero_empty_tiles(B, out);
     const ItemMap im(B.hdr->counter, per_wg);
     for (int64_t u = im.first; u < im.n; u += im.step) {
         const int b = (int)(u % per_wg) * wpb + wv;
@@ -834,6 +846,7 @@ __global__ __launch_bounds__(256) void k_query_region(DevBatch B, int cap, int m
     L.ctl = reinterpret_cast<int *>(L.mask + RS * (RS / 32));
     L.scan = reinterpret_cast<uint32_t *>(L.ctl + 4);
     uint8_t *const out = B.hdr->out;
+    zero_empty_tiles(B, out);
     const ItemMap im(B.hdr->counter, RPT);
     for (int64_t u = im.first; u < im.n; u += im.step) {
         const int64_t t = B.list[im.pos(u, RPT)];
@@ -875,7 +888,8 @@ Workspace workspace_layout(int64_t n_req, int n_ix) {
     w.frontier_off = w.req_off + align256(sizeof(DevReq) * (size_t)n_req);
     w.fmeta_off = w.frontier_off + align256(sizeof(uint32_t) * kFrontier * (size_t)n_req);
     w.list_off = w.fmeta_off + align256(sizeof(int32_t) * 2 * (size_t)n_req);
-    w.done_off = w.list_off + align256(sizeof(uint32_t) * (size_t)n_req);
+    w.elist_off = w.list_off + align256(sizeof(uint32_t) * (size_t)n_req);
+    w.done_off = w.elist_off + align256(sizeof(uint32_t) * (size_t)n_req);
     w.ts_off = w.done_off + align256(sizeof(uint32_t) * (size_t)n_req);
     w.total = w.ts_off + align256(sizeof(uint64_t) * (size_t)n_req);
     return w;
@@ -900,6 +914,7 @@ DevBatch device_batch(const Workspace &w, unsigned char *dws) {
     b.frontier = reinterpret_cast<uint32_t *>(dws + w.frontier_off);
     b.fmeta = reinterpret_cast<int32_t *>(dws + w.fmeta_off);
     b.list = reinterpret_cast<uint32_t *>(dws + w.list_off);
+    b.elist = reinterpret_cast<uint32_t *>(dws + w.elist_off);
     b.done = reinterpret_cast<uint32_t *>(dws + w.done_off);
     b.ts = reinterpret_cast<uint64_t *>(dws + w.ts_off);
     return b;
@@ -935,11 +950,14 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
 }
 
 hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,
-                        hipStream_t st) {
+                        hipStream_t st, hipEvent_t *marks) {
     const int64_t n_req = w.n_req;  // requests the grids cover; the header holds how many are live
     if (n_req == 0) return hipSuccess;
     const DevBatch B = device_batch(w, dws);
+    hipError_t e;
+    if (marks && (e = hipEventRecord(marks[0], st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B);
+    if (marks && (e = hipEventRecord(marks[1], st)) != hipSuccess) return e;
     const size_t lds = query_lds_bytes(s, max_levels);
     // never more workgroups than there are blocks (or regions) to render
     const int64_t per_tile = s.region ? (256 / s.region) * (256 / s.region)
@@ -953,7 +971,9 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, 
     else if (s.block == 8) hipLaunchKernelGGL(k_query<8>, g, b, lds, st, B, s.cand_cap, max_levels);
     else if (s.block == 16) hipLaunchKernelGGL(k_query<16>, g, b, lds, st, B, s.cand_cap, max_levels);
     else hipLaunchKernelGGL(k_query<32>, g, b, lds, st, B, s.cand_cap, max_levels);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (marks && (e = hipEventRecord(marks[2], st)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 }  // namespace hv

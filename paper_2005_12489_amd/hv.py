@@ -40,7 +40,8 @@ HV_MAX_ZOOM = 22
 
 SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free", "hv_last_error",
            "hv_set_stream", "hv_index_info", "hv_index_read", "hv_render_batch", "hv_batcher_create",
-           "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch")
+           "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch",
+           "hv_time_kernels")
 
 # hv_request as a numpy record (32 bytes, the C layout)
 REQUEST_DTYPE = np.dtype([("index", np.uint64), ("z", np.int32), ("x", np.int32), ("y", np.int32),
@@ -112,6 +113,9 @@ lib.hv_autotune.restype = ctypes.c_int
 lib.hv_autotune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.POINTER(ctypes.c_double)]
 lib.hv_tuned_launch.restype = ctypes.c_int
 lib.hv_tuned_launch.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(hv_launch)]
+lib.hv_time_kernels.restype = ctypes.c_int
+lib.hv_time_kernels.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_double)]
 
 
 def _check(rc: int) -> int:
@@ -303,6 +307,18 @@ def hv_tuned_launch(reqs):
     L = hv_launch()
     rc = lib.hv_tuned_launch(r.ctypes.data_as(_P), r.shape[0], ctypes.byref(L))
     return _launch_dict(L) if rc == HV_OK else None
+
+
+def hv_time_kernels(reqs, out_masks, launch=None, reps: int = 10):
+    """Mean (frontier kernel ms, query kernel ms) over reps renders of the
+    batch, from HIP events on the current stream."""
+    r = _reqs(reqs)
+    L = _launch(launch)
+    ms = (ctypes.c_double * 2)()
+    _sync_stream()
+    _check(lib.hv_time_kernels(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks),
+                               ctypes.byref(L) if L else None, int(reps), ms))
+    return ms[0], ms[1]
 
 
 # ------------------------------------------------------------ convenience

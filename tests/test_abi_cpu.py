@@ -107,5 +107,11 @@ def test_batch_validation_before_any_device_call(hv):
         with pytest.raises(hv.HvError, match="empty"):
             hv.hv_autotune(hv.requests(h, np.zeros((0, 3)), 1.0), 1)
         assert hv.hv_tuned_launch(hv.requests(h, [(3, 1, 1)], 1.0)) is None
+        for reqs, reps, msg in [(hv.requests(h, np.zeros((0, 3)), 1.0), 1, "empty"),
+                                (hv.requests(h, [(3, 1, 1)], 1.0), 0, "reps"),
+                                (hv.requests(h, [(3, 1, 1)], 1.0), 100001, "reps"),
+                                (hv.requests(h, [(3, 1, 1)], 0.0), 1, "r_px")]:
+            with pytest.raises(hv.HvError, match=msg):
+                hv.hv_time_kernels(reqs, 1, reps=reps)
     finally:
         hv.hv_free(h)
