@@ -88,7 +88,7 @@ struct DevBatch {
     const DevIndex *ixs;
     const DevReq *reqs;
     uint32_t *frontier;  // per request: up to 256 frontier nodes
-    int32_t *fmeta;      // per request: frontier size, frontier level
+    int32_t *fmeta;      // per request: frontier size, frontier level, 64 bits of regions it reaches
     uint32_t *list;      // compacted list of requests with data nearby
     uint32_t *elist;     // requests whose tile has no data within r
     uint32_t *done;      // per request: parts finished

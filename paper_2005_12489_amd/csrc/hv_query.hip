@@ -65,7 +65,37 @@ __device__ inline bool meets(const double4 &nb, double qx0, double qx1, double q
     return nb.x <= qx1 && nb.z >= qx0 && nb.y <= qy1 && nb.w >= qy0;
 }
 
-__global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
+// Regions of side rs (32 or 64) of a tile whose query box -- pixel centres
+// grown by m -- a node box meets: bit ry * (256 / rs) + rx.  The region
+// kernel makes the same test in normalised coordinates; this one, in tile
+// pixels, is widened by 1e-6 px so that it never misses a region that test
+// would find (rounding differs by at most ~1e-7 px up to zoom 22).
+__device__ inline uint64_t region_bits(const double4 &nb, double S, double ox, double oy, double m, int rs) {
+    const double nr = 256.0 / rs, e = 1e-6;
+    const double fx0 = fmax(ceil((nb.x * S - ox - (rs - 0.5) - m - e) / rs), 0.0);
+    const double fx1 = fmin(floor((nb.z * S - ox - 0.5 + m + e) / rs), nr - 1.0);
+    const double fy0 = fmax(ceil((nb.y * S - oy - (rs - 0.5) - m - e) / rs), 0.0);
+    const double fy1 = fmin(floor((nb.w * S - oy - 0.5 + m + e) / rs), nr - 1.0);
+    if (!(fx0 <= fx1 && fy0 <= fy1)) return 0;
+    const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1, n = (int)nr;
+    const uint64_t row = ((1ull << (x1 - x0 + 1)) - 1ull) << x0;
+    uint64_t bits = 0;
+    for (int y = y0; y <= y1; ++y) bits |= row << (y * n);
+    return bits;
+}
+
+__device__ inline uint64_t wave_or64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, 64), hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+        v |= (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+    return v;
+}
+
+// rs: region side of the query kernel that follows (32 or 64), for which the
+// frontier records the regions its nodes can reach; 0 marks every part.
+__global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs) {
     __shared__ uint32_t buf[4][2][kFrontier];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps per-tile values scalar
@@ -74,29 +104,39 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
     if (t >= B.hdr->n_req) return;
     const DevReq rq = B.reqs[t];
     const DevIndex ix = B.ixs[rq.index];
-    const double iS = ldexp(1.0, -8 - rq.z);
+    const double iS = ldexp(1.0, -8 - rq.z), S = ldexp(256.0, rq.z);
     const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
     const double m = rq.r + kCullPad;
     const double qx0 = (ox + (0.5 - m)) * iS, qx1 = (ox + (255.5 + m)) * iS;
     const double qy0 = (oy + (0.5 - m)) * iS, qy1 = (oy + (255.5 + m)) * iS;
     uint32_t *cur = buf[wv][0], *nxt = buf[wv][1];
     int ncur = 0, lvl = ix.levels - 1;
-    if (ix.levels > 0 && meets(ix.nodes[ix.meta[ix.levels - 1]], qx0, qx1, qy0, qy1)) {
-        if (lane == 0) cur[0] = 0;
-        ncur = 1;
+    uint64_t cbits = ~0ull;  // regions the current frontier level can reach
+    if (ix.levels > 0) {
+        const double4 root = ix.nodes[ix.meta[ix.levels - 1]];
+        if (meets(root, qx0, qx1, qy0, qy1)) {
+            if (lane == 0) cur[0] = 0;
+            ncur = 1;
+            if (rs) cbits = region_bits(root, S, ox, oy, m, rs);
+        }
     }
     __builtin_amdgcn_wave_barrier();
     while (lvl > 0 && ncur > 0) {
         const int cl = lvl - 1;
         const int64_t cnt = ix.meta[kMaxLevels + cl], off = ix.meta[cl];
         int nn = 0;
+        uint64_t nbits = 0;
         for (int base = 0; base < ncur * kFan; base += 64) {
             const int k = base + lane;
             bool hit = false;
             int64_t child = 0;
             if (k < ncur * kFan) {
                 child = (int64_t)cur[k / kFan] * kFan + (k % kFan);
-                hit = child < cnt && meets(ix.nodes[off + child], qx0, qx1, qy0, qy1);
+                if (child < cnt) {
+                    const double4 nb = ix.nodes[off + child];
+                    hit = meets(nb, qx0, qx1, qy0, qy1);
+                    if (hit && rs) nbits |= region_bits(nb, S, ox, oy, m, rs);
+                }
             }
             const uint64_t hm = __ballot(hit);
             const int pos = nn + (int)lanes_below(hm);
@@ -110,6 +150,7 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
         cur = nxt;
         nxt = tmp;
         ncur = nn;
+        if (rs) cbits = wave_or64(nbits);
         --lvl;
     }
     if (ncur == 0) {
@@ -120,8 +161,7 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B) {
     }
     for (int k = lane; k < ncur; k += 64) B.frontier[t * kFrontier + k] = cur[k];
     if (lane == 0) {
-        B.fmeta[2 * t] = ncur;
-        B.fmeta[2 * t + 1] = lvl;
+        reinterpret_cast<int4 *>(B.fmeta)[t] = make_int4(ncur, lvl, (int)(uint32_t)cbits, (int)(uint32_t)(cbits >> 32));
         B.done[t] = 0;
         B.list[atomicAdd(&B.hdr->counter, 1)] = (uint32_t)t;
     }
@@ -227,7 +267,7 @@ __device__ __forceinline__ void block_query(const DevIndex &ix, const DevReq &rq
     bool all_lit = false;
     {
         // the tile's frontier, tested against the block's box in rounds of 64
-        const int fcount = fmeta[2 * t], flevel = fmeta[2 * t + 1];
+        const int fcount = fmeta[4 * t], flevel = fmeta[4 * t + 1];
         for (int base = 0; base < fcount; base += 64) {
             bool hit = false;
             uint32_t node = 0;
@@ -570,6 +610,17 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
     const double qx1 = ((ox + i0) + ((RS - 0.5) + m)) * iS;
     const double qy0 = ((oy + j0) + (0.5 - m)) * iS;
     const double qy1 = ((oy + j0) + ((RS - 0.5) + m)) * iS;
+    uint8_t *tm = out + t * (int64_t)HV_MASK_BYTES;
+
+    const int4 fm = reinterpret_cast<const int4 *>(fmeta)[t];
+    const int fcount = fm.x, flevel = fm.y;
+    const uint64_t reach = (uint64_t)(uint32_t)fm.z | ((uint64_t)(uint32_t)fm.w << 32);
+    if (!((reach >> reg) & 1ull)) {
+        // no frontier node comes within r of this region: all zero
+        for (int k = tid; k < RS * W; k += nthr)
+            *reinterpret_cast<uint32_t *>(tm + (ry * RS + k / W) * 32 + rx * (RS / 8) + 4 * (k % W)) = 0u;
+        return;
+    }
 
     for (int k = tid; k < RS * W; k += nthr) mask[k] = 0;
     if (tid == 0) {
@@ -577,22 +628,30 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         ctl[1] = 0;
     }
     __syncthreads();
-    const int fcount = fmeta[2 * t], flevel = fmeta[2 * t + 1];
-    // pushes the frontier nodes that meet the region
-    auto push_frontier = [&]() {
+    // edge accepts keep a margin so that they never claim a pixel whose
+    // distance could round to just above r
+    const double racc = r - 1e-7, racc2 = racc * racc;
+    // Pushes the frontier nodes that meet the region; true when one of them
+    // is worth an accept pass: its leaves, at about 4^-level of its size,
+    // could be small enough to light pixels by themselves.
+    auto push_frontier = [&]() -> bool {
+        bool promising = false;
         for (int base = 0; base < fcount; base += nthr) {
             bool hit = false;
             uint32_t node = 0;
             if (base + tid < fcount) {
                 node = frontier[t * kFrontier + base + tid];
-                hit = meets(ix.nodes[ix.meta[flevel] + node], qx0, qx1, qy0, qy1);
+                const double4 nb = ix.nodes[ix.meta[flevel] + node];
+                hit = meets(nb, qx0, qx1, qy0, qy1);
+                const double w = (nb.z - nb.x) * S, h = (nb.w - nb.y) * S;
+                promising |= hit && w * w + h * h <= ldexp(16.0 * racc2, 4 * flevel);
             }
             const int pos = wave_alloc(&ctl[0], __ballot(hit), lane);
             if (hit) stk[pos] = ((uint32_t)flevel << kLevelShift) | node;
         }
-        __syncthreads();
+        return __syncthreads_or(promising);
     };
-    push_frontier();
+    const bool promising = push_frontier();
 
     // Tests every queued object against its pixels; returns true once the
     // whole region is lit.
@@ -633,8 +692,13 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                 inv = L.ci[lo];
             }
             const double wy = (j0 + (double)row + 0.5) - a.y;
+            // only the cell's pixels not lit yet (pixels are only ever set)
+            const int wbase = c0 & ~31;
+            uint32_t todo = (((2u << (c1 - c0)) - 1u) << (c0 - wbase)) & ~mask[row * W + (wbase >> 5)];
             uint32_t bits = 0;
-            for (int ii = c0; ii <= c1; ++ii) {
+            while (todo) {
+                const int ii = wbase + __builtin_ctz(todo);
+                todo &= todo - 1u;
                 const double wx = (i0 + (double)ii + 0.5) - a.x;
                 double d2;
                 if (SEG) {
@@ -658,16 +722,14 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         return all;
     };
 
-    // edge accepts keep a margin so that they never claim a pixel whose
-    // distance could round to just above r
-    const double racc = r - 1e-7, racc2 = racc * racc;
     // Two walks.  The first (accept pass) descends only until nodes are small
     // enough for their edge accepts to cover the pixels around them, makes
     // those accepts and reads no objects; it skips subtrees whose leaves are
     // unlikely to be that small.  In dense data it lights most pixels, so
     // that the second, full walk finds most ranges lit and reads few objects.
-    // A frontier made of leaves takes the full walk only.
-    bool accept_pass = racc > 0.0 && flevel > 0;
+    // A frontier made of leaves, or of nodes whose leaves cannot be small,
+    // takes the full walk only.
+    bool accept_pass = racc > 0.0 && flevel > 0 && promising;
     bool done = false;
     for (;;) {
         const int sp = ctl[0];
@@ -676,7 +738,7 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
             accept_pass = false;
             // every wave has read the empty stack before any pushes to it
             __syncthreads();
-            push_frontier();
+            (void)push_frontier();
             continue;
         }
         bool accepted = false;
@@ -821,7 +883,6 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
     }
     if (!done && ctl[1] > 0) drain();
     __syncthreads();
-    uint8_t *tm = out + t * (int64_t)HV_MASK_BYTES;
     for (int k = tid; k < RS * W; k += nthr) {
         const int row = k / W, wd = k % W;
         *reinterpret_cast<uint32_t *>(tm + (ry * RS + row) * 32 + rx * (RS / 8) + 4 * wd) = mask[k];
@@ -887,7 +948,7 @@ Workspace workspace_layout(int64_t n_req, int n_ix) {
     w.req_off = w.table_off + align256(sizeof(DevIndex) * (size_t)n_ix);
     w.frontier_off = w.req_off + align256(sizeof(DevReq) * (size_t)n_req);
     w.fmeta_off = w.frontier_off + align256(sizeof(uint32_t) * kFrontier * (size_t)n_req);
-    w.list_off = w.fmeta_off + align256(sizeof(int32_t) * 2 * (size_t)n_req);
+    w.list_off = w.fmeta_off + align256(sizeof(int32_t) * 4 * (size_t)n_req);
     w.elist_off = w.list_off + align256(sizeof(uint32_t) * (size_t)n_req);
     w.done_off = w.elist_off + align256(sizeof(uint32_t) * (size_t)n_req);
     w.ts_off = w.done_off + align256(sizeof(uint32_t) * (size_t)n_req);
@@ -956,7 +1017,7 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, 
     const DevBatch B = device_batch(w, dws);
     hipError_t e;
     if (marks && (e = hipEventRecord(marks[0], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B, s.region);
     if (marks && (e = hipEventRecord(marks[1], st)) != hipSuccess) return e;
     const size_t lds = query_lds_bytes(s, max_levels);
     // never more workgroups than there are blocks (or regions) to render

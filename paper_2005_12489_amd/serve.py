@@ -34,9 +34,10 @@ MASK_BYTES = 8192
 
 def workspace_bytes_per_request() -> int:
     """Device workspace one request occupies in a batch: request record (24 B),
-    frontier (256 x 4 B), frontier size and level (8 B), work-list and
-    empty-list entries (2 x 4 B), completion counter (4 B) and stamp (8 B)."""
-    return 24 + 256 * 4 + 8 + 4 + 4 + 4 + 8
+    frontier (256 x 4 B), frontier size, level and region bits (16 B),
+    work-list and empty-list entries (2 x 4 B), completion counter (4 B) and
+    stamp (8 B)."""
+    return 24 + 256 * 4 + 16 + 4 + 4 + 4 + 8
 
 
 @dataclass
