@@ -179,19 +179,30 @@ def serve_bench(args, hv, torch):
         torch.cuda.empty_cache()
         stage(f"index built over {objs.shape[0]} objects")
     levels = max(hv.hv_index_info(h)["levels"] for h in hs)
+    roots = [hv.hv_index_info(h)["root"] for h in hs]
     del pts
     rows = []
     for rate in RATES:
         arr = hvgen.c5_arrivals(rate, c2_objects=segs)
         reqs = hv.requests(np.where(arr["dataset"] == 0, hs[0], hs[1]).astype(np.uint64), arr["tiles"], arr["r"])
         row = {"rate": rate, "requests": len(reqs)}
-        for mode, mb in (("batched", 4096), ("per_request", 1)):
-            ex = serve.GpuExecutor(reqs, streams=2, max_batch=mb, max_indexes=2, max_levels=levels)
+        keyed = {"dataset": arr["dataset"], "tiles": arr["tiles"], "r": arr["r"]}
+        for mode, mb in (("batched", 4096), ("per_request", 1), ("batched_cached", 4096)):
+            cached = mode == "batched_cached"
+            ex = serve.GpuExecutor(reqs, streams=2, max_batch=mb, max_indexes=2, max_levels=levels,
+                                   return_masks=cached)
             warm = np.arange(min(64, len(reqs)))
             serve.serve(np.zeros(len(warm)), serve.Scheduler(max_batch=mb), _Subset(ex, warm))
-            st = serve.serve(arr["t"], serve.Scheduler(max_batch=mb), ex)
+            extra = {}
+            if cached:
+                extra = {"requests": keyed, "parser": serve.RequestParser(roots),
+                         "cache": serve.ResultCache(cap_bytes=1 << 30, ttl_s=60.0)}
+            st = serve.serve(arr["t"], serve.Scheduler(max_batch=mb), ex, **extra)
             ex.close()
-            row[mode] = {k: st[k] for k in ("tiles_per_s", "p50_ms", "p99_ms", "max_ms", "batches", "mean_batch")}
+            keys = ("tiles_per_s", "p50_ms", "p99_ms", "max_ms", "batches", "mean_batch")
+            if cached:
+                keys += ("tasks", "cache_hits", "joined", "empty", "rejected")
+            row[mode] = {k: st[k] for k in keys}
             stage(f"rate {rate:g}/s {mode}: {st['tiles_per_s']:.0f} tiles/s p99 {st['p99_ms']:.2f} ms")
         print(json.dumps({"serving_rate": rate, **row}), file=sys.stderr, flush=True)
         rows.append(row)
@@ -205,8 +216,9 @@ def serve_bench(args, hv, torch):
         "config": {"workload": WORKLOADS["c5"]["name"], "n_segments": int(segs.shape[0]), "n_points": n3,
                    "rates_per_s": list(RATES), "streams": 2, "max_batch": 4096},
         "serving": rows,
-        "note": "value = served tiles/s at the highest offered rate; latency = completion (masks on the "
-                "host) - scheduled arrival",
+        "note": "value = served tiles/s at the highest offered rate without the result pool; latency = "
+                "completion (masks on the host) - scheduled arrival; batched_cached adds the parse rules, "
+                "the result pool (1 GiB, 60 s) and joining of duplicate requests",
     }
     print(json.dumps(rec))
 
@@ -224,10 +236,7 @@ class _Subset:
         self.ex.launch(lane, self.ids[np.asarray(ids)])
 
     def poll(self):
-        out = []
-        for ids, t in self.ex.poll():
-            out.append((np.searchsorted(self.ids, ids), t))
-        return out
+        return [(np.searchsorted(self.ids, r[0]), *r[1:]) for r in self.ex.poll()]
 
 
 def main():

@@ -53,3 +53,42 @@ def test_served_equals_alone_and_oracle(hv, torch):
         assert parity(served[sel], tri)[0] == 0, d
     hv.hv_free(h2)
     hv.hv_free(h3)
+
+
+def test_served_with_parse_rules_and_cache_equals_alone(hv, torch):
+    """Parse rules, result pool and joined duplicates change only which
+    requests make tasks: every served mask still equals the request rendered
+    alone."""
+    from paper_2005_12489_amd import serve
+    segs = hvgen.gen_c2_segments(n_segments=200_000)
+    pts = hvgen.gen_c3_points(200_000)
+    rng = np.random.default_rng(9)
+    small = np.stack([rng.uniform(10.0, 12.0, 2000), rng.uniform(40.0, 42.0, 2000)], 1)
+    hs = [build(hv, torch, segs, hv.HV_SEGMENTS), build(hv, torch, pts, hv.HV_POINTS),
+          build(hv, torch, small, hv.HV_POINTS)]
+    arr = hvgen.c5_arrivals(20000.0, c2_objects=segs, max_requests=3000, zmax=8)
+    n = len(arr["t"])
+    ds = arr["dataset"].copy()
+    ds[::10] = 2                        # a tenth go to the small set: mostly outside its box
+    req = {"dataset": ds, "tiles": arr["tiles"], "r": arr["r"]}
+    reqs = hv.requests(np.array(hs, dtype=np.uint64)[ds], arr["tiles"], arr["r"])
+    parser = serve.RequestParser([hv.hv_index_info(h)["root"] for h in hs])
+    cache = serve.ResultCache(cap_bytes=64 << 20, ttl_s=60.0)
+    ex = serve.GpuExecutor(reqs, streams=2, max_batch=512, max_indexes=3, max_levels=12, keep_masks=True,
+                           return_masks=True)
+    log(f"serve with parse rules and cache: {n} requests")
+    st = serve.serve(arr["t"], serve.Scheduler(max_batch=512), ex, requests=req, parser=parser, cache=cache)
+    ex.close()
+    log(f"tasks={st['tasks']} hits={st['cache_hits']} joined={st['joined']} empty={st['empty']} "
+        f"p50={st['p50_ms']:.3f} ms p99={st['p99_ms']:.3f} ms")
+    assert st["cache_hits"] > 0 and st["empty"] > 0 and st["tasks"] < n
+    assert st["tasks"] + st["cache_hits"] + st["joined"] + st["empty"] + st["rejected"] == n
+    served = unpack_masks(ex.masks)
+    alone = torch.empty((n, 8192), dtype=torch.uint8, device="cuda")
+    hv.hv_render_batch(reqs, alone)
+    torch.cuda.synchronize()
+    ref = unpack_masks(alone.cpu().numpy())
+    for k in range(n):
+        assert np.array_equal(ref[k], served[k]), (k, int(st["status"][k]))
+    for h in hs:
+        hv.hv_free(h)

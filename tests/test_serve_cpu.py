@@ -20,10 +20,11 @@ class SimClock:
 
 
 class FakeExecutor:
-    def __init__(self, clock, lanes=2, a=200e-6, b=2e-6):
+    def __init__(self, clock, lanes=2, a=200e-6, b=2e-6, mask_of=None):
         self.clock, self.a, self.b = clock, a, b
         self.busy = [None] * lanes
         self.launched = []
+        self.mask_of = mask_of
 
     def idle_lane(self):
         for k, x in enumerate(self.busy):
@@ -40,7 +41,9 @@ class FakeExecutor:
         out = []
         for k, x in enumerate(self.busy):
             if x is not None and x[1] <= self.clock.t:
-                out.append((np.asarray(x[0]), x[1]))
+                ids = np.asarray(x[0])
+                rows = np.stack([self.mask_of(i) for i in ids]) if self.mask_of else None
+                out.append((ids, x[1], rows))
                 self.busy[k] = None
         return out
 
@@ -84,3 +87,101 @@ def test_light_load_latency_is_one_launch():
     st, ex, *_ = _run(100.0, 200)
     # at 100 req/s nearly every request is launched alone and waits ~a + b
     assert st["p50_ms"] < 0.3
+
+
+# ------------------------------------------------------------ parse rules, result pool
+def test_parser_rejects_wrong_expressions_and_empties_tiles_outside_the_data():
+    # dataset 0: a box in the north-west quadrant whose east edge lies 12 px
+    # (at z = 4) west of tile x = 4; dataset 1: an empty index
+    P = serve_mod.RequestParser([(0.1, 0.1, 0.25 - 12.0 / 4096, 0.2), None])
+    T, E, R = serve_mod.TASK, serve_mod.EMPTY, serve_mod.REJECT
+    assert P.classify(0, 0, 0, 0, 1.0) == T
+    assert P.classify(2, 0, 0, 0, 1.0) == R                  # unknown dataset
+    assert P.classify(0, 23, 0, 0, 1.0) == R                 # zoom
+    assert P.classify(0, 3, 8, 0, 1.0) == R                  # x outside [0, 2^z)
+    assert P.classify(0, 3, 0, -1, 1.0) == R
+    for r in (0.0, -1.0, 64.5, float("nan"), float("inf")):
+        assert P.classify(0, 3, 0, 0, r) == R
+    assert P.classify(1, 3, 0, 0, 1.0) == E                  # empty index
+    assert P.classify(0, 3, 7, 7, 1.0) == E                  # far from the box
+    assert P.classify(0, 3, 0, 0, 1.0) == T                  # tile [0, 1/8)^2 holds the box
+    # z = 4: tile x = 3 covers [3/16, 4/16) and meets the box (0.1..0.2)
+    assert P.classify(0, 4, 3, 3, 1.0) == T
+    # the nearest pixel centre of tile (4, 4, 2) is 12.5 px east of the box:
+    # empty for r = 12, a task for r = 13
+    assert P.classify(0, 4, 4, 2, 12.0) == E
+    assert P.classify(0, 4, 4, 2, 13.0) == T
+
+
+def test_cache_hits_expire_and_are_cleaned_only_past_the_cap():
+    m = lambda v: np.full(8192, v, dtype=np.uint8)
+    C = serve_mod.ResultCache(cap_bytes=3 * 8192, ttl_s=10.0)
+    C.put("a", m(1), 0.0)
+    C.put("b", m(2), 1.0)
+    assert C.get("a", 5.0)[0] == 1 and C.hits == 1
+    assert C.get("a", 10.5) is None                          # expired: no longer answers
+    assert len(C) == 2                                       # but kept until the cap is reached
+    C.put("c", m(3), 11.0)
+    assert len(C) == 3 and C.bytes == 3 * 8192 and C.expired_cleaned == 0
+    C.put("d", m(4), 11.5)                                   # past the cap: expired "a", "b" go
+    assert C.expired_cleaned == 2 and C.evicted == 0 and set(C._d) == {"c", "d"}
+    C.put("e", m(5), 12.0)
+    C.put("f", m(6), 12.5)                                   # nothing expired: oldest ("c") goes
+    assert C.evicted == 1 and set(C._d) == {"d", "e", "f"} and C.bytes <= C.cap_bytes
+    C.put("d", m(7), 13.0)                                   # re-store refreshes the entry
+    assert C.get("d", 22.0)[0] == 7 and C.bytes == 3 * 8192
+
+
+def _keyed_stream(n, seed, n_keys):
+    rng = np.random.default_rng(seed)
+    k = rng.integers(0, n_keys, n)
+    tiles = np.stack([np.full(n, 10), k % 1024, k // 1024], 1)
+    return {"dataset": np.zeros(n, int), "tiles": tiles, "r": np.full(n, 1.5)}
+
+
+def test_served_with_parse_rules_cache_and_joined_duplicates():
+    n = 4000
+    req = _keyed_stream(n, 3, 300)
+    # an invalid and an out-of-bounds request among them
+    req["r"][7] = -1.0
+    req["tiles"][11] = (10, 1023, 1023)
+    rng = np.random.default_rng(4)
+    arr = np.cumsum(rng.exponential(1.0 / 40000.0, n))
+    clk = SimClock()
+
+    def mask_of(i):
+        z, x, y = req["tiles"][i]
+        return np.full(8192, (x * 7 + y) % 251, dtype=np.uint8)
+
+    ex = FakeExecutor(clk, mask_of=mask_of)
+    ex.masks = np.zeros((n, 8192), dtype=np.uint8)
+    sch = serve_mod.Scheduler()
+    parser = serve_mod.RequestParser([(0.0, 0.0, 0.5, 0.5)])
+    cache = serve_mod.ResultCache(cap_bytes=1 << 30, ttl_s=1e9)
+    st = serve_mod.serve(arr, sch, ex, clock=clk, sleep=clk.sleep, requests=req, parser=parser, cache=cache)
+    launched = np.concatenate([np.asarray(b) for b in ex.launched])
+    keys = [tuple(req["tiles"][i]) for i in launched]
+    assert len(keys) == len(set(keys))                       # each key rendered once
+    assert st["tasks"] == len(launched)
+    assert st["rejected"] == 1 and st["empty"] == 1 and st["status"][7] == serve_mod.REJECT
+    assert st["status"][11] == serve_mod.EMPTY and not ex.masks[11].any()
+    assert st["tasks"] + st["cache_hits"] + st["joined"] + 2 == n
+    assert st["joined"] > 0 and st["cache_hits"] > 0
+    assert np.all(np.isfinite(st["latency_s"])) and np.all(st["latency_s"] >= 0)
+    for i in range(n):
+        if st["status"][i] == serve_mod.TASK:
+            assert np.array_equal(ex.masks[i], mask_of(i)), i
+    assert sch.inflight == 0 and sch.mem_used == 0
+
+
+def test_expired_results_make_new_tasks():
+    n = 600
+    req = _keyed_stream(n, 5, 20)
+    arr = np.linspace(0.0, 0.6, n)
+    clk = SimClock()
+    ex = FakeExecutor(clk, mask_of=lambda i: np.zeros(8192, dtype=np.uint8))
+    cache = serve_mod.ResultCache(ttl_s=0.05)
+    st = serve_mod.serve(arr, serve_mod.Scheduler(), ex, clock=clk, sleep=clk.sleep, requests=req,
+                         parser=serve_mod.RequestParser([(0.0, 0.0, 1.0, 1.0)]), cache=cache)
+    # 20 keys over 0.6 s with a 50 ms window: each key is rendered several times
+    assert 20 < st["tasks"] < n and st["cache_hits"] > 0
