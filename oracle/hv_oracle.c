@@ -445,3 +445,231 @@ int oracle_render(const void *h, const int32_t *tiles, int64_t ntiles, const dou
     for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
     return jb.err ? -1 : 0;
 }
+
+/* ---------------------------------------------------- anti-aliased output */
+/*
+ * Algorithm 1 in full (Sec. 3.2.1) gives every pixel a value 0-4: the number
+ * of its four sub-samples, at the pixel centre +- 1/4 px in x and in y, that
+ * lie in the rasterised zone of radius r.
+ *
+ * OR_AA_EXACT -- the plain definition: value = #{ s : D(s) <= r }, D the
+ *   distance from sub-sample s to the nearest object.  Each sub-sample gets
+ *   its own box query s +- (r + pad).  amb = the number of sub-samples whose
+ *   D lies within 1e-6 px of r; lit_sure = the number with D < r - 1e-6.
+ *   (Algorithm 1's early answers follow from it: D(P) <= R1 puts every
+ *   sub-sample within r, D(P) > R2 puts none.)
+ *
+ * OR_AA_PAPER -- Algorithm 1's steps as printed, in px (R_z = 1):
+ *   R1 = r - sqrt(2)/4, R2 = r + sqrt(2)/4, h = sqrt(2)/2 * R1.
+ *   1. An object meeting InnerBox_1 = P +- h answers 4.
+ *   2. Otherwise the object nearest to P among those meeting OuterBox_1 =
+ *      P +- R1: if it lies within R1 of P, 4.
+ *   3. Otherwise the nearest object Tmp among those meeting OuterBox_2 =
+ *      P +- R2: if it lies within R2 of P, the number of sub-samples within
+ *      r of Tmp.
+ *   4. Otherwise 0.
+ *   Reading: when several objects are equally near, Tmp is the one with the
+ *   smallest input index.  Only the nearest object to the centre is used for
+ *   the sub-samples, so this can count fewer sub-samples than OR_AA_EXACT.
+ *   amb = 1 for a pixel where a comparison of step 2, 3 or 4 lies within
+ *   1e-6 px of its threshold, or where another object is within 1e-6 px of
+ *   Tmp's distance; lit_sure is unused (0).
+ */
+#define OR_AA_EXACT 0
+#define OR_AA_PAPER 1
+
+/* Distance from (px,py) to every object meeting the square (px,py) +- h, in
+ * the tile-local pixel frame; returns the smallest and, if kmin is not NULL,
+ * the smallest input index attaining it, plus the second-smallest distance
+ * among other objects in *d2nd (INFINITY if none). */
+static double nearest_in_box(const or_index *ix, double S, double ox, double oy, double px, double py,
+                             double h, int64_t *kmin, double *d2nd, int64_t *stack)
+{
+    const double cx = ox + px, cy = oy + py;
+    obox q = { (cx - h) / S, (cy - h) / S, (cx + h) / S, (cy + h) / S };
+    double D = INFINITY, D2 = INFINITY;
+    int64_t best = -1;
+    int64_t sp = 0;
+    if (ix->root >= 0 && h >= 0.0) stack[sp++] = ix->root;
+    while (sp > 0) {
+        int64_t nd = stack[--sp];
+        if (!box_meets(&ix->box[nd], &q)) continue;
+        const int64_t *ch = ix->child + ix->first[nd];
+        if (!ix->leaf[nd]) {
+            for (int32_t c = 0; c < ix->count[nd]; ++c) stack[sp++] = ch[c];
+            continue;
+        }
+        for (int32_t c = 0; c < ix->count[nd]; ++c) {
+            int64_t k = ch[c];
+            obox b = obj_box(ix, k);
+            if (!box_meets(&b, &q)) continue;
+            double d = obj_dist(ix, k, S, ox, oy, px, py);
+            if (d < D || (d == D && k < best)) {
+                if (best >= 0 && D < D2) D2 = D;
+                D = d;
+                best = k;
+            } else if (d < D2) {
+                D2 = d;
+            }
+        }
+    }
+    if (kmin) *kmin = best;
+    if (d2nd) *d2nd = D2;
+    return D;
+}
+
+/* True when object k meets the closed square [x0,x1] x [y0,y1] (tile px). */
+static int obj_meets_square(const or_index *ix, int64_t k, double S, double ox, double oy,
+                            double x0, double y0, double x1, double y1)
+{
+    double ax = ix->ax[k] * S - ox, ay = ix->ay[k] * S - oy;
+    if (ix->kind == OR_POINTS) return ax >= x0 && ax <= x1 && ay >= y0 && ay <= y1;
+    double bx = ix->bx[k] * S - ox, by = ix->by[k] * S - oy;
+    /* clip the segment a + t (b - a), t in [0, 1], against each slab */
+    double t0 = 0.0, t1 = 1.0;
+    const double d[2] = { bx - ax, by - ay }, a[2] = { ax, ay }, lo[2] = { x0, y0 }, hi[2] = { x1, y1 };
+    for (int c = 0; c < 2; ++c) {
+        if (d[c] == 0.0) {
+            if (a[c] < lo[c] || a[c] > hi[c]) return 0;
+            continue;
+        }
+        double u = (lo[c] - a[c]) / d[c], v = (hi[c] - a[c]) / d[c];
+        if (u > v) { double w = u; u = v; v = w; }
+        if (u > t0) t0 = u;
+        if (v < t1) t1 = v;
+        if (t0 > t1) return 0;
+    }
+    return 1;
+}
+
+static int inner_box_hit(const or_index *ix, double S, double ox, double oy, double px, double py,
+                         double h, int64_t *stack)
+{
+    if (!(h >= 0.0) || ix->root < 0) return 0;
+    const double cx = ox + px, cy = oy + py;
+    obox q = { (cx - h) / S, (cy - h) / S, (cx + h) / S, (cy + h) / S };
+    int64_t sp = 0;
+    stack[sp++] = ix->root;
+    while (sp > 0) {
+        int64_t nd = stack[--sp];
+        if (!box_meets(&ix->box[nd], &q)) continue;
+        const int64_t *ch = ix->child + ix->first[nd];
+        if (!ix->leaf[nd]) {
+            for (int32_t c = 0; c < ix->count[nd]; ++c) stack[sp++] = ch[c];
+            continue;
+        }
+        for (int32_t c = 0; c < ix->count[nd]; ++c)
+            if (obj_meets_square(ix, ch[c], S, ox, oy, px - h, py - h, px + h, py + h)) return 1;
+    }
+    return 0;
+}
+
+static int render_tile_aa(const or_index *ix, int z, int64_t tx, int64_t ty, double r, int mode,
+                          uint8_t *val, uint8_t *amb, uint8_t *sure, int64_t *stack)
+{
+    const double S = ldexp(256.0, z);
+    const double ox = (double)tx * 256.0, oy = (double)ty * 256.0;
+    const double q4 = sqrt(2.0) / 4.0;
+    const double R1 = r - q4, R2 = r + q4, h = sqrt(2.0) / 2.0 * R1;
+    static const double sx[4] = { -0.25, 0.25, -0.25, 0.25 }, sy[4] = { 0.25, 0.25, -0.25, -0.25 };
+    for (int j = 0; j < 256; ++j) {
+        for (int i = 0; i < 256; ++i) {
+            const double px = 0.5 + i, py = 0.5 + j;
+            const size_t p = (size_t)(256 * j + i);
+            uint8_t v = 0, a = 0, su = 0;
+            if (mode == OR_AA_EXACT) {
+                for (int s = 0; s < 4; ++s) {
+                    double D = nearest_in_box(ix, S, ox, oy, px + sx[s], py + sy[s], r + OR_QUERY_PAD,
+                                              NULL, NULL, stack);
+                    v += D <= r;
+                    a += fabs(D - r) <= OR_BAND;
+                    su += D < r - OR_BAND;
+                }
+            } else {
+                if (inner_box_hit(ix, S, ox, oy, px, py, h, stack)) {
+                    v = 4;                                            /* step 1 */
+                } else {
+                    int64_t k = -1;
+                    double D2;
+                    double D = nearest_in_box(ix, S, ox, oy, px, py, R1, &k, &D2, stack);
+                    if (k >= 0 && D <= R1) {
+                        v = 4;                                        /* step 2 */
+                        a = fabs(D - R1) <= OR_BAND;
+                    } else {
+                        D = nearest_in_box(ix, S, ox, oy, px, py, R2, &k, &D2, stack);
+                        if (k >= 0 && D <= R2) {                      /* step 3 */
+                            for (int s = 0; s < 4; ++s) {
+                                double d = obj_dist(ix, k, S, ox, oy, px + sx[s], py + sy[s]);
+                                v += d <= r;
+                                a |= fabs(d - r) <= OR_BAND;
+                            }
+                            a |= fabs(D - R2) <= OR_BAND || fabs(D - R1) <= OR_BAND || D2 - D <= OR_BAND;
+                        } else if (k >= 0) {
+                            a = fabs(D - R2) <= OR_BAND;              /* step 4 */
+                        }
+                    }
+                }
+            }
+            val[p] = v;
+            if (amb) amb[p] = a;
+            if (sure) sure[p] = su;
+        }
+    }
+    return 0;
+}
+
+typedef struct {
+    const or_index *ix;
+    const int32_t *tiles;
+    const double *r;
+    int64_t ntiles;
+    int mode;
+    uint8_t *val, *amb, *sure;
+    int64_t next;
+    int err;
+} job_aa;
+
+static void *worker_aa(void *arg)
+{
+    job_aa *jb = (job_aa *)arg;
+    int64_t *stack = malloc(sizeof(int64_t) * (size_t)OR_FANOUT * (size_t)(jb->ix->depth + 2));
+    if (!stack) { __atomic_store_n(&jb->err, 1, __ATOMIC_RELAXED); return NULL; }
+    for (;;) {
+        int64_t t = __atomic_fetch_add(&jb->next, 1, __ATOMIC_RELAXED);
+        if (t >= jb->ntiles) break;
+        const int32_t *tl = jb->tiles + 3 * t;
+        size_t off = (size_t)t * 65536;
+        render_tile_aa(jb->ix, tl[0], tl[1], tl[2], jb->r[t], jb->mode, jb->val + off,
+                       jb->amb ? jb->amb + off : NULL, jb->sure ? jb->sure + off : NULL, stack);
+    }
+    free(stack);
+    return NULL;
+}
+
+/* Anti-aliased values 0-4 per pixel (see above).  tiles, r as for
+ * oracle_render; val (required), amb and sure (optional) are ntiles x 65536
+ * bytes, row-major from the north-west pixel.  Returns 0, or -1 on a bad
+ * argument or allocation failure. */
+int oracle_render_aa(const void *h, const int32_t *tiles, int64_t ntiles, const double *r, int mode,
+                     uint8_t *val, uint8_t *amb, uint8_t *sure, int nthreads)
+{
+    const or_index *ix = (const or_index *)h;
+    if (!ix || ntiles < 0 || (ntiles > 0 && (!tiles || !r || !val))) return -1;
+    if (mode != OR_AA_EXACT && mode != OR_AA_PAPER) return -1;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int32_t z = tiles[3 * t], x = tiles[3 * t + 1], y = tiles[3 * t + 2];
+        if (z < 0 || z > 30 || x < 0 || y < 0 || (int64_t)x >= ((int64_t)1 << z) ||
+            (int64_t)y >= ((int64_t)1 << z) || !(r[t] > 0.0) || !isfinite(r[t]))
+            return -1;
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    job_aa jb = { ix, tiles, r, ntiles, mode, val, amb, sure, 0, 0 };
+    pthread_t th[256];
+    int started = 0;
+    for (int k = 1; k < nthreads; ++k)
+        if (pthread_create(&th[started], NULL, worker_aa, &jb) == 0) ++started;
+    worker_aa(&jb);
+    for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
+    return jb.err ? -1 : 0;
+}

@@ -33,12 +33,13 @@ def objects_merc01(objects: np.ndarray, kind: int) -> np.ndarray:
 
 
 def brute_distance(objs: np.ndarray, kind: int, z: int, x: int, y: int,
-                   chunk: int = 64) -> np.ndarray:
-    """D (256,256) [row j][column i]; objs are normalised Mercator."""
+                   chunk: int = 64, off: tuple = (0.0, 0.0)) -> np.ndarray:
+    """D (256,256) [row j][column i] at the pixel centres shifted by ``off``
+    (px, e.g. an anti-aliasing sub-sample); objs are normalised Mercator."""
     S = 256.0 * 2.0 ** z
     cols = np.arange(256, dtype=np.float64) + 0.5
-    PX = np.tile(cols, 256)[:, None]          # column i of pixel p
-    PY = np.repeat(cols, 256)[:, None]        # row j of pixel p
+    PX = np.tile(cols + off[0], 256)[:, None]          # column i of pixel p
+    PY = np.repeat(cols + off[1], 256)[:, None]        # row j of pixel p
     best = np.full((65536, 1), np.inf)
     if kind == 0:
         o = np.asarray(objs, dtype=np.float64).reshape(-1, 2)

@@ -11,6 +11,9 @@ Kinds of pins used (paper sections in brackets):
   library        -- scipy cKDTree nearest-neighbour distance [points]
   invariants     -- union, permutation, monotone in r, own pixel,
                     parent-empty => child-empty, tile translation
+  anti-aliasing  -- sub-sample lattice counts, exact ties, a two-point case
+                    where Algorithm 1's printed step undercounts, brute force
+                    over sub-samples, one zoom deeper at twice the radius
 """
 from __future__ import annotations
 
@@ -322,6 +325,88 @@ def pin_invariants(lib_path=None):
         assert np.array_equal(o1["tri"], o2["tri"]), ("translation", kind)
 
 
+# ------------------------------------------------------------ anti-aliased output
+SUB = ((-0.25, 0.25), (0.25, 0.25), (-0.25, -0.25), (0.25, -0.25))   # Algorithm 1's sub-samples
+
+
+def _odd_lattice_count(r: float) -> int:
+    """Sub-samples of the whole plane within r of a point on a pixel centre:
+    points ((2k+1)/4, (2l+1)/4), counted with integers."""
+    lim = 16.0 * r * r
+    m = int(4 * r) + 2
+    return sum(1 for k in range(-m, m) for l in range(-m, m) if (2 * k + 1) ** 2 + (2 * l + 1) ** 2 <= lim)
+
+
+def pin_aa_lattice(lib_path=None):
+    """One point on a pixel centre: the values summed over the tile are the
+    quarter-odd lattice count; the pixel itself is 4 once r >= sqrt(2)/4."""
+    z, x, y = 6, 20, 30
+    u, v = 128.5, 100.5
+    X, Y = _px_to_merc(z, x, y, u, v)
+    ix = _ix([[X, Y]], oracle.POINTS, lib_path=lib_path)
+    for r in (0.3, 0.4, 0.8, 1.0, 1.1, 1.6, 2.0, 3.3):
+        ex = ix.render_aa([[z, x, y]], r)
+        pa = ix.render_aa([[z, x, y]], r, mode="paper")
+        assert int(ex["val"].sum()) == _odd_lattice_count(r), ("aa lattice", r)
+        assert int(ex["val"][0, 100, 128]) == (4 if r >= math.sqrt(2) / 4 else 0), ("aa own pixel", r)
+        assert not ex["amb"].any() and np.array_equal(ex["sure"], ex["val"]), ("aa no ties", r)
+        assert np.array_equal(pa["val"], ex["val"]), ("aa one object: paper = exact", r)
+
+
+def pin_aa_ties_and_paper(lib_path=None):
+    """Exact ties count (inclusive); the printed step undercounts where a
+    sub-sample's nearest object is not the centre's."""
+    z, x, y = 0, 0, 0
+    # a point exactly 0.5 px east of the north-east sub-sample of pixel (100, 80)
+    cu, cv = 100.5, 80.5
+    X, Y = _px_to_merc(z, x, y, cu + 0.25 + 0.5, cv - 0.25)
+    ex = _ix([[X, Y]], oracle.POINTS, lib_path=lib_path).render_aa([[z, x, y]], 0.5)
+    assert ex["amb"][0, 80, 100] == 1 and ex["val"][0, 80, 100] == 1 and ex["sure"][0, 80, 100] == 0
+    # two points: A 0.625 px east of the centre (the nearest), B 0.640625 px
+    # west; r = 0.5 px puts the centre in the transition band (R1 < 0.625 < R2)
+    A = _px_to_merc(z, x, y, cu + 0.625, cv)
+    B = _px_to_merc(z, x, y, cu - 0.640625, cv)
+    ix = _ix([[A[0], A[1]], [B[0], B[1]]], oracle.POINTS, lib_path=lib_path)
+    ex = ix.render_aa([[z, x, y]], 0.5)
+    pa = ix.render_aa([[z, x, y]], 0.5, mode="paper")
+    assert ex["val"][0, 80, 100] == 4, "east pair from A, west pair from B"
+    assert pa["val"][0, 80, 100] == 2, "only A (the centre's nearest) is measured"
+    assert not ex["amb"][0, 80, 100] and not pa["amb"][0, 80, 100]
+
+
+def pin_aa_brute(lib_path=None, n_obj=120, seed=21):
+    """Every object against every sub-sample (numpy), and the identity with
+    binary masks one zoom deeper at twice the radius (the sub-samples are
+    exactly that zoom's pixel centres)."""
+    rng = np.random.default_rng(seed)
+    for kind in (oracle.POINTS, oracle.SEGMENTS):
+        for (z, x, y), r in (((3, 2, 5), 0.5), ((7, 40, 77), 1.3), ((12, 2000, 1500), 2.5)):
+            objs = _random_objects(rng, kind, z, x, y, n_obj)
+            ix = _ix(objs, kind, lib_path=lib_path)
+            ex = ix.render_aa([[z, x, y]], r)
+            val = np.zeros((256, 256), dtype=np.int32)
+            edge = np.zeros((256, 256), dtype=bool)
+            for off in SUB:
+                D = brute_distance(objs, kind, z, x, y, off=off)
+                val += D <= r
+                edge |= near_band_edge(D, r)
+            ok = ~edge
+            assert np.array_equal(ex["val"][0][ok], val[ok]), ("aa brute", kind, z, r)
+            kids = [(z + 1, 2 * x + dx, 2 * y + dy) for dy in (0, 1) for dx in (0, 1)]
+            b = ix.render(kids, 2 * r)["bit"].reshape(2, 2, 256, 256)
+            full = np.block([[b[0, 0], b[0, 1]], [b[1, 0], b[1, 1]]]).astype(np.int32)
+            s4 = full.reshape(256, 2, 256, 2).sum(axis=(1, 3))
+            assert np.array_equal(s4, ex["val"][0]), ("aa = deeper zoom at 2r", kind, z, r)
+            pa = ix.render_aa([[z, x, y]], r, mode="paper")
+            assert np.all(pa["val"] <= ex["val"]), ("paper <= exact", kind, z, r)
+            # Algorithm 1's early answers: D(P) <= R1 -> 4, D(P) > R2 -> 0
+            D0 = brute_distance(objs, kind, z, x, y)
+            q = math.sqrt(2) / 4
+            inner, outer = D0 < r - q - 1e-9, D0 > r + q + 1e-9
+            assert np.all(ex["val"][0][inner] == 4) and np.all(pa["val"][0][inner] == 4), ("R1", kind)
+            assert np.all(ex["val"][0][outer] == 0) and np.all(pa["val"][0][outer] == 0), ("R2", kind)
+
+
 PINS = {
     "projection": pin_projection,
     "addressing": pin_addressing,
@@ -330,4 +415,7 @@ PINS = {
     "kinds": pin_kinds,
     "brute": pin_brute,
     "invariants": pin_invariants,
+    "aa_lattice": pin_aa_lattice,
+    "aa_ties_and_paper": pin_aa_ties_and_paper,
+    "aa_brute": pin_aa_brute,
 }

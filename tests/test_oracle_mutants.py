@@ -35,6 +35,12 @@ MUTANTS = [
     ("edges-as-points", "if (ix->kind == OR_POINTS) {\n        double ex", "if (ix->kind != OR_SEGMENTS) {\n        double ex"),
     ("segment-b-is-a", "ix->bx[q] = (w == 4) ? o[2] : o[0];", "ix->bx[q] = o[0];"),
     ("box-meets-axis", "b->y0 <= a->y1;", "b->y0 <= a->x1;"),
+    ("aa-sub-offset", "sx[4] = { -0.25, 0.25, -0.25, 0.25 }", "sx[4] = { -0.5, 0.5, -0.5, 0.5 }"),
+    ("aa-strict", "v += D <= r;", "v += D < r;"),
+    ("aa-r1-sign", "const double R1 = r - q4,", "const double R1 = r + q4,"),
+    ("aa-inner-box", "h = sqrt(2.0) / 2.0 * R1;", "h = sqrt(2.0) * R1;"),
+    ("aa-not-nearest", "if (d < D || (d == D && k < best)) {", "if (best < 0 || k < best) {"),
+    ("aa-transposed", "const size_t p = (size_t)(256 * j + i);", "const size_t p = (size_t)(256 * i + j);"),
 ]
 
 
