@@ -250,6 +250,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-tile", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-aa", action="store_true", help="skip the anti-aliased (0-4) output figure")
     ap.add_argument("--launch", default="", help="JSON hv_launch fields, e.g. '{\"region\": 64}'")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes per step (HBM counter calibration)")
@@ -330,6 +331,22 @@ def main():
     torch.cuda.synchronize()
     plain = n * 5 / (time.perf_counter() - p0)
 
+    # Algorithm 1's anti-aliased output (one byte per pixel) for the same requests
+    aa = None
+    if not args.no_aa:
+        out_aa = torch.empty((n, hv.HV_AA_BYTES), dtype=torch.uint8, device="cuda")
+        hv.hv_render_batch_aa(reqs, out_aa, launch)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for _ in range(5):
+            hv.hv_render_batch_aa(reqs, out_aa, launch)
+        torch.cuda.synchronize()
+        aa_s = (time.perf_counter() - a0) / 5
+        aa = {"tiles_per_s": n / aa_s, "ms_per_call": aa_s * 1e3,
+              "note": "values 0-4 per pixel: the four children one zoom deeper at 2r, 2 x 2 sums"}
+        del out_aa
+        stage(f"anti-aliased: {n / aa_s:.0f} tiles/s")
+
     per_tile = None
     if not args.no_per_tile:
         m = min(n, 4096)
@@ -384,6 +401,7 @@ def main():
                     "note": "one graph launch per step; a request's latency is its completion "
                             "after the batch started on the device"},
         "plain_call_tiles_per_s": plain,
+        "anti_aliased": aa,
         "per_tile_launch": per_tile,
         "autotune_ms": tuned_ms,
         "build_ms": info["build_ms"],

@@ -58,6 +58,8 @@ enum { HV_OK = 0, HV_EINVAL = -1, HV_ENOMEM = -2, HV_EHIP = -3 };
 /* Largest object count (sorted positions are 32-bit). */
 #define HV_MAX_OBJECTS 2000000000LL
 #define HV_MASK_BYTES 8192
+/* Bytes of one anti-aliased tile: one value 0-4 per pixel. */
+#define HV_AA_BYTES 65536
 
 typedef struct hv_index hv_index;
 
@@ -227,6 +229,24 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
 /* The cached shape for a batch's class: HV_OK and *out filled, or HV_EINVAL
  * if that class has not been tuned. */
 int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
+
+/* Anti-aliased output: Algorithm 1's value 0-4 per pixel (Sec. 3.2.1), the
+ * number of the pixel's four sub-samples -- its centre +- 1/4 px in x and y
+ * -- that lie within r of some object of the request's index, each
+ * sub-sample measured against its own nearest object (Algorithm 1 as
+ * printed measures all four against the object nearest the centre, which
+ * can count fewer).  The sub-samples of tile (z, x, y) are the pixel centres
+ * of its four children at zoom z + 1, where the radius is 2r, so the library
+ * renders those binary masks with the kernels of hv_render_batch into
+ * stream-ordered scratch (4 x 8192 bytes per request, freed in stream order)
+ * and sums each pixel's 2 x 2 bits.
+ * reqs: host array as for hv_render_batch, with z <= HV_MAX_ZOOM - 1.
+ * out_values: device, n * HV_AA_BYTES bytes, 16-byte aligned; the value of
+ * pixel (i, j) of request k is at k * HV_AA_BYTES + j * 256 + i.
+ * launch: the query shape (NULL = the default shape).  Asynchronous on the
+ * calling thread's stream.  Errors as hv_render_batch, plus HV_EINVAL for
+ * z = HV_MAX_ZOOM; nothing is launched on error. */
+int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch);
 
 /* Kernel timing for roofline figures.  Renders the batch reps times, as
  * hv_render_batch would (same arguments; launch NULL takes the tuned shape

@@ -118,6 +118,11 @@ DevBatch device_batch(const Workspace &w, unsigned char *dws);
 hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,
                         hipStream_t stream, hipEvent_t *marks = nullptr);
 
+// Sums the 2 x 2 sub-sample bits of each pixel from four child masks per
+// request (one zoom deeper, child 2 * dy + dx) into n anti-aliased tiles of
+// HV_AA_BYTES at `out` (device), on `stream`.
+hipError_t launch_aa_reduce(const uint8_t *child_masks, int64_t n, uint8_t *out, hipStream_t stream);
+
 // Workgroups that fill the current device for a shape (occupancy x CUs).
 int persistent_grid(const LaunchShape &s, int max_levels);
 

@@ -920,6 +920,33 @@ __global__ __launch_bounds__(256) void k_query_region(DevBatch B, int cap, int m
     }
 }
 
+// ------------------------------------------------------------ anti-aliasing
+// Algorithm 1's value 0-4 per pixel counts the pixel's four sub-samples
+// (centre +- 1/4 px in x and y) within r.  Those sub-samples are exactly the
+// pixel centres of the tile's four children one zoom deeper, where r is 2r
+// (every coordinate doubles exactly), so the value is the sum of the pixel's
+// 2 x 2 bits in the children's masks.  child_masks: 4 per request, child
+// 2 * dy + dx = tile (z + 1, 2x + dx, 2y + dy).  One thread per four output
+// pixels: child row bytes b0 (row 2j') and b1 (row 2j' + 1) hold the 8
+// sub-sample columns of those pixels.
+__global__ __launch_bounds__(256) void k_aa_reduce(const uint8_t *__restrict__ child_masks, int64_t n,
+                                                   uint8_t *__restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n * (HV_AA_BYTES / 4)) return;
+    const int64_t k = g / (HV_AA_BYTES / 4);
+    const int w = (int)(g % (HV_AA_BYTES / 4));
+    const int j = w >> 6, q = w & 63;           // row, group of pixels 4q .. 4q + 3
+    const int dy = j >> 7, dx = q >> 5;
+    const uint8_t *c = child_masks + (k * 4 + dy * 2 + dx) * (int64_t)HV_MASK_BYTES;
+    const int row = 2 * (j & 127), col = q & 31;
+    const uint32_t b0 = c[row * 32 + col], b1 = c[(row + 1) * 32 + col];
+    uint32_t v = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        v |= (uint32_t)(__popc((b0 >> (2 * m)) & 3u) + __popc((b1 >> (2 * m)) & 3u)) << (8 * m);
+    reinterpret_cast<uint32_t *>(out + k * (int64_t)HV_AA_BYTES)[w] = v;
+}
+
 using RegionKernel = void (*)(DevBatch, int, int);
 
 RegionKernel region_kernel(const LaunchShape &s) {
@@ -1008,6 +1035,13 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
     const int grid = 10 * per_cu * cus;
     if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, s.region, s.opl, lds, grid};
     return grid;
+}
+
+hipError_t launch_aa_reduce(const uint8_t *child_masks, int64_t n, uint8_t *out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int64_t words = n * (HV_AA_BYTES / 4);
+    hipLaunchKernelGGL(k_aa_reduce, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, child_masks, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,

@@ -36,12 +36,13 @@ HV_INPUT_MERC01 = 0x100
 HV_OK, HV_EINVAL, HV_ENOMEM, HV_EHIP = 0, -1, -2, -3
 HV_READ_ORDER, HV_READ_OBJECTS, HV_READ_NODES = 0, 1, 2
 HV_MASK_BYTES = 8192
+HV_AA_BYTES = 65536
 HV_MAX_ZOOM = 22
 
 SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free", "hv_last_error",
            "hv_set_stream", "hv_index_info", "hv_index_read", "hv_render_batch", "hv_batcher_create",
            "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch",
-           "hv_time_kernels")
+           "hv_time_kernels", "hv_render_batch_aa")
 
 # hv_request as a numpy record (32 bytes, the C layout)
 REQUEST_DTYPE = np.dtype([("index", np.uint64), ("z", np.int32), ("x", np.int32), ("y", np.int32),
@@ -113,6 +114,8 @@ lib.hv_autotune.restype = ctypes.c_int
 lib.hv_autotune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.POINTER(ctypes.c_double)]
 lib.hv_tuned_launch.restype = ctypes.c_int
 lib.hv_tuned_launch.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(hv_launch)]
+lib.hv_render_batch_aa.restype = ctypes.c_int
+lib.hv_render_batch_aa.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
 lib.hv_time_kernels.restype = ctypes.c_int
 lib.hv_time_kernels.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_double)]
@@ -261,6 +264,16 @@ def hv_render_batch(reqs, out_masks, launch=None) -> None:
     _sync_stream()
     _check(lib.hv_render_batch(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks),
                                ctypes.byref(L) if L else None))
+
+
+def hv_render_batch_aa(reqs, out_values, launch=None) -> None:
+    """Anti-aliased values 0-4 (one byte per pixel, HV_AA_BYTES per request)
+    into the device buffer out_values."""
+    r = _reqs(reqs)
+    L = _launch(launch)
+    _sync_stream()
+    _check(lib.hv_render_batch_aa(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_values),
+                                  ctypes.byref(L) if L else None))
 
 
 def hv_batcher_create(max_requests: int, max_indexes: int = 8, max_levels: int = 10, launch=None) -> int:
