@@ -60,6 +60,12 @@ def _bind(lib):
     lib.oracle_depth.argtypes = [P]
     lib.oracle_root_box.restype = ctypes.c_int
     lib.oracle_root_box.argtypes = [P, P]
+    lib.oracle_build_polygons.restype = P
+    lib.oracle_build_polygons.argtypes = [P, I64, P, I64, ctypes.c_int]
+    lib.oracle_free_polygons.restype = None
+    lib.oracle_free_polygons.argtypes = [P]
+    lib.oracle_render_fill.restype = ctypes.c_int
+    lib.oracle_render_fill.argtypes = [P, P, I64, P, P, ctypes.c_int]
     lib.oracle_render_aa.restype = ctypes.c_int
     lib.oracle_render_aa.argtypes = [P, P, I64, P, ctypes.c_int, P, P, P, ctypes.c_int]
     return lib
@@ -165,3 +171,36 @@ class OracleIndex:
         if sure is not None:
             out["sure"] = sure
         return out
+
+
+class OraclePolygons:
+    """Polygon filling (Sec. 3.2.2, Algorithm 2) on the CPU: edges (n, 4)
+    lon0, lat0, lon1, lat1 (or normalised Mercator with merc01=True);
+    polygon p owns edges first[p] .. first[p+1]-1, which form closed rings."""
+
+    def __init__(self, edges, first, merc01: bool = False, lib_path: str | None = None):
+        self._lib = _load(lib_path)
+        e = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1, 4)
+        f = np.ascontiguousarray(first, dtype=np.int64)
+        self._keep = (e, f)
+        self._h = self._lib.oracle_build_polygons(_ptr(e), e.shape[0], _ptr(f), f.shape[0] - 1, int(merc01))
+        if not self._h:
+            raise ValueError("oracle_build_polygons rejected its arguments")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.oracle_free_polygons(h)
+            self._h = None
+
+    def render(self, tiles, nthreads: int | None = None):
+        """Returns dict 'tri' (0 outside, 1 inside, 2 within 1e-6 px of an
+        edge) and 'bit' (inside some polygon), each (n, 256, 256) u8."""
+        t = np.ascontiguousarray(tiles, dtype=np.int32).reshape(-1, 3)
+        n = t.shape[0]
+        tri = np.empty((n, 256, 256), dtype=np.uint8)
+        bit = np.empty((n, 256, 256), dtype=np.uint8)
+        th = default_threads() if nthreads is None else nthreads
+        if self._lib.oracle_render_fill(self._h, _ptr(t), n, _ptr(tri), _ptr(bit), th) != 0:
+            raise ValueError("oracle_render_fill rejected its arguments")
+        return {"tri": tri, "bit": bit}

@@ -673,3 +673,194 @@ int oracle_render_aa(const void *h, const int32_t *tiles, int64_t ntiles, const 
     for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
     return jb.err ? -1 : 0;
 }
+
+/* ------------------------------------------------------- polygon filling */
+/*
+ * SIBF (Sec. 3.2.2, Algorithm 2): a pixel is filled when its centre lies
+ * inside some polygon.  The plain definition used here: for every polygon
+ * whose bounding box holds the centre c, count the polygon's edges that a
+ * ray from c towards +x crosses, with the half-open rule in y (an edge
+ * (a, b) is crossed when exactly one of a.y, b.y is greater than c.y, and
+ * the crossing lies at x > c.x), so that a vertex on the ray is counted
+ * once and edges parallel to x never (Algorithm 2's IsLevel edges and
+ * segment cutting do the same).  An odd count puts c inside that polygon
+ * (even-odd rule: rings inside rings are holes).  The pixel is filled if c
+ * is inside any polygon.
+ *
+ * Algorithm 2 casts its ray towards the nearer side of the polygon's box;
+ * for closed rings the parity does not depend on the direction.
+ *
+ * Tri-state: 1 when c is inside some polygon and farther than 1e-6 px from
+ * its edges; otherwise 2 (ambiguous) when c lies within 1e-6 px of an edge of
+ * a candidate polygon; otherwise 0.  bit = [inside some polygon].
+ *
+ * Polygons: npoly groups of edges, polygon p owning edges [first[p],
+ * first[p+1]) of the (n, 4) edge array; each group must form closed rings.
+ */
+typedef struct {
+    or_index *mbr;                 /* STR tree over the polygons' bounding boxes */
+    int64_t npoly, n;
+    int64_t *first;                /* npoly + 1 */
+    double *ax, *ay, *bx, *by;     /* normalised Mercator, input order */
+} or_poly;
+
+void oracle_free_polygons(void *h)
+{
+    or_poly *P = (or_poly *)h;
+    if (!P) return;
+    if (P->mbr) oracle_free(P->mbr);
+    free(P->first); free(P->ax); free(P->ay); free(P->bx); free(P->by);
+    free(P);
+}
+
+void *oracle_build_polygons(const double *edges, int64_t n, const int64_t *first, int64_t npoly, int merc01)
+{
+    if (n < 0 || npoly < 0 || (npoly > 0 && !first) || (n > 0 && !edges)) return NULL;
+    if (npoly > 0 && (first[0] != 0 || first[npoly] != n)) return NULL;
+    for (int64_t p = 0; p < npoly; ++p)
+        if (first[p + 1] - first[p] < 3) return NULL;     /* a ring needs three edges */
+    or_poly *P = calloc(1, sizeof(or_poly));
+    if (!P) return NULL;
+    P->npoly = npoly;
+    P->n = n;
+    size_t sz = (size_t)(n > 0 ? n : 1) * sizeof(double);
+    P->first = malloc((size_t)(npoly + 1) * sizeof(int64_t));
+    P->ax = malloc(sz); P->ay = malloc(sz); P->bx = malloc(sz); P->by = malloc(sz);
+    double *mb = malloc((size_t)(npoly > 0 ? npoly : 1) * 4 * sizeof(double));
+    if (!P->first || !P->ax || !P->ay || !P->bx || !P->by || !mb) {
+        free(mb); oracle_free_polygons(P); return NULL;
+    }
+    for (int64_t p = 0; p <= npoly; ++p) P->first[p] = npoly > 0 ? first[p] : 0;
+    for (int64_t q = 0; q < n; ++q) {
+        const double *o = edges + 4 * q;
+        if (merc01) { P->ax[q] = o[0]; P->ay[q] = o[1]; P->bx[q] = o[2]; P->by[q] = o[3]; }
+        else { project_one(o[0], o[1], &P->ax[q], &P->ay[q]); project_one(o[2], o[3], &P->bx[q], &P->by[q]); }
+    }
+    for (int64_t p = 0; p < npoly; ++p) {
+        double x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+        for (int64_t q = first[p]; q < first[p + 1]; ++q) {
+            x0 = fmin(x0, fmin(P->ax[q], P->bx[q])); x1 = fmax(x1, fmax(P->ax[q], P->bx[q]));
+            y0 = fmin(y0, fmin(P->ay[q], P->by[q])); y1 = fmax(y1, fmax(P->ay[q], P->by[q]));
+        }
+        mb[4 * p] = x0; mb[4 * p + 1] = y0; mb[4 * p + 2] = x1; mb[4 * p + 3] = y1;
+    }
+    /* the box of a diagonal segment is the polygon's box */
+    P->mbr = oracle_build(mb, OR_SEGMENTS | OR_MERC01, npoly);
+    free(mb);
+    if (!P->mbr) { oracle_free_polygons(P); return NULL; }
+    return P;
+}
+
+/* Distance (px) from (cx, cy) to edge q, tile-local frame. */
+static double edge_dist(const or_poly *P, int64_t q, double S, double ox, double oy, double cx, double cy)
+{
+    double ax = P->ax[q] * S - ox, ay = P->ay[q] * S - oy;
+    double bx = P->bx[q] * S - ox, by = P->by[q] * S - oy;
+    double dx = bx - ax, dy = by - ay, len2 = dx * dx + dy * dy, t = 0.0;
+    if (len2 > 0.0) {
+        t = ((cx - ax) * dx + (cy - ay) * dy) / len2;
+        if (t < 0.0) t = 0.0;
+        t = fmin(t, 1.0);
+    }
+    double ex = cx - (ax + t * dx), ey = cy - (ay + t * dy);
+    return sqrt(ex * ex + ey * ey);
+}
+
+static void fill_tile(const or_poly *P, int z, int64_t tx, int64_t ty, uint8_t *tri, uint8_t *bit, int64_t *stack)
+{
+    const double S = ldexp(256.0, z);
+    const double ox = (double)tx * 256.0, oy = (double)ty * 256.0;
+    const or_index *M = P->mbr;
+    for (int j = 0; j < 256; ++j) {
+        for (int i = 0; i < 256; ++i) {
+            const double cx = i + 0.5, cy = j + 0.5;            /* tile-local centre */
+            const double wx = ox + cx, wy = oy + cy;             /* world pixels */
+            const double g = OR_BAND;
+            obox q = { (wx - g) / S, (wy - g) / S, (wx + g) / S, (wy + g) / S };
+            int inside_sure = 0, inside_any = 0, near = 0;
+            int64_t sp = 0;
+            if (M->root >= 0) stack[sp++] = M->root;
+            while (sp > 0 && !inside_sure) {
+                int64_t nd = stack[--sp];
+                if (!box_meets(&M->box[nd], &q)) continue;
+                const int64_t *ch = M->child + M->first[nd];
+                if (!M->leaf[nd]) {
+                    for (int32_t c = 0; c < M->count[nd]; ++c) stack[sp++] = ch[c];
+                    continue;
+                }
+                for (int32_t c = 0; c < M->count[nd] && !inside_sure; ++c) {
+                    const int64_t p = ch[c];
+                    obox b = obj_box(M, p);
+                    if (!box_meets(&b, &q)) continue;
+                    int par = 0;
+                    double dmin = INFINITY;
+                    for (int64_t e = P->first[p]; e < P->first[p + 1]; ++e) {
+                        double ay = P->ay[e] * S - oy, by = P->by[e] * S - oy;
+                        if ((ay > cy) != (by > cy)) {
+                            double ax = P->ax[e] * S - ox, bx = P->bx[e] * S - ox;
+                            double x = ax + (cy - ay) * (bx - ax) / (by - ay);
+                            if (x > cx) par ^= 1;
+                        }
+                        double d = edge_dist(P, e, S, ox, oy, cx, cy);
+                        if (d < dmin) dmin = d;
+                    }
+                    if (par) inside_any = 1;
+                    if (dmin <= OR_BAND) near = 1;
+                    else if (par) inside_sure = 1;
+                }
+            }
+            const size_t at = (size_t)j * 256 + (size_t)i;
+            tri[at] = inside_sure ? 1 : (near ? 2 : 0);
+            if (bit) bit[at] = (uint8_t)(inside_sure || inside_any);
+        }
+    }
+}
+
+typedef struct {
+    const or_poly *P;
+    const int32_t *tiles;
+    int64_t ntiles;
+    uint8_t *tri, *bit;
+    int64_t next;
+    int err;
+} job_fill;
+
+static void *worker_fill(void *arg)
+{
+    job_fill *jb = (job_fill *)arg;
+    int64_t *stack = malloc(sizeof(int64_t) * (size_t)OR_FANOUT * (size_t)(jb->P->mbr->depth + 2));
+    if (!stack) { __atomic_store_n(&jb->err, 1, __ATOMIC_RELAXED); return NULL; }
+    for (;;) {
+        int64_t t = __atomic_fetch_add(&jb->next, 1, __ATOMIC_RELAXED);
+        if (t >= jb->ntiles) break;
+        const int32_t *tl = jb->tiles + 3 * t;
+        size_t off = (size_t)t * 65536;
+        fill_tile(jb->P, tl[0], tl[1], tl[2], jb->tri + off, jb->bit ? jb->bit + off : NULL, stack);
+    }
+    free(stack);
+    return NULL;
+}
+
+/* Fill masks of polygons (see above).  tiles as for oracle_render; tri
+ * (required) and bit (optional) are ntiles x 65536 bytes, row-major from
+ * the north-west pixel.  Returns 0, or -1 on a bad argument. */
+int oracle_render_fill(const void *h, const int32_t *tiles, int64_t ntiles, uint8_t *tri, uint8_t *bit, int nthreads)
+{
+    const or_poly *P = (const or_poly *)h;
+    if (!P || ntiles < 0 || (ntiles > 0 && (!tiles || !tri))) return -1;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int32_t z = tiles[3 * t], x = tiles[3 * t + 1], y = tiles[3 * t + 2];
+        if (z < 0 || z > 30 || x < 0 || y < 0 || (int64_t)x >= ((int64_t)1 << z) || (int64_t)y >= ((int64_t)1 << z))
+            return -1;
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    job_fill jb = { P, tiles, ntiles, tri, bit, 0, 0 };
+    pthread_t th[256];
+    int started = 0;
+    for (int k = 1; k < nthreads; ++k)
+        if (pthread_create(&th[started], NULL, worker_fill, &jb) == 0) ++started;
+    worker_fill(&jb);
+    for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
+    return jb.err ? -1 : 0;
+}

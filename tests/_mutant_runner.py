@@ -11,7 +11,10 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 import oracle_pins  # noqa: E402
 
 lib = sys.argv[1]
-for name, fn in oracle_pins.PINS.items():
+# optional: a name prefix of the pins to try first (the planted mistake's family)
+first = sys.argv[2] if len(sys.argv) > 2 else ""
+order = sorted(oracle_pins.PINS.items(), key=lambda kv: not (first and kv[0].startswith(first)))
+for name, fn in order:
     try:
         fn(lib_path=lib)
     except AssertionError as e:

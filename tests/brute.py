@@ -73,3 +73,32 @@ def tri_state(D: np.ndarray, r: float) -> np.ndarray:
 def near_band_edge(D: np.ndarray, r: float, tol: float = 1e-9) -> np.ndarray:
     """Pixels whose classification could flip under last-bit rounding."""
     return (np.abs(D - (r - BAND)) <= tol) | (np.abs(D - (r + BAND)) <= tol) | (np.abs(D - r) <= tol)
+
+
+def brute_fill(edges: np.ndarray, first, z: int, x: int, y: int):
+    """Polygon fill by brute force: for every polygon, the parity of its edges
+    crossed by a ray from each pixel centre towards -x (half-open in y), then
+    OR over polygons.  Returns (inside (256,256) bool, distance (256,256) from
+    each centre to the nearest edge, px).  edges: normalised Mercator (n, 4)."""
+    S = 256.0 * 2.0 ** z
+    e = np.asarray(edges, dtype=np.float64).reshape(-1, 4)
+    ax, ay = e[:, 0] * S - 256.0 * x, e[:, 1] * S - 256.0 * y
+    bx, by = e[:, 2] * S - 256.0 * x, e[:, 3] * S - 256.0 * y
+    c = np.arange(256, dtype=np.float64) + 0.5
+    CX, CY = np.meshgrid(c, c)                       # [row j][column i]
+    inside = np.zeros((256, 256), dtype=bool)
+    dist = np.full((256, 256), np.inf)
+    for p in range(len(first) - 1):
+        par = np.zeros((256, 256), dtype=bool)
+        for q in range(first[p], first[p + 1]):
+            cross = (ay[q] > CY) != (by[q] > CY)
+            if cross.any():
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    xc = ax[q] + (CY - ay[q]) * (bx[q] - ax[q]) / (by[q] - ay[q])
+                par ^= cross & (xc < CX)
+            dx, dy = bx[q] - ax[q], by[q] - ay[q]
+            l2 = dx * dx + dy * dy
+            t = np.clip(((CX - ax[q]) * dx + (CY - ay[q]) * dy) / l2, 0.0, 1.0) if l2 > 0 else 0.0
+            dist = np.minimum(dist, np.hypot(CX - (ax[q] + t * dx), CY - (ay[q] + t * dy)))
+        inside |= par
+    return inside, dist

@@ -23,7 +23,7 @@ import os
 import numpy as np
 
 import oracle
-from brute import brute_distance, near_band_edge, objects_merc01, tri_state
+from brute import brute_distance, brute_fill, near_band_edge, objects_merc01, tri_state
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -407,6 +407,116 @@ def pin_aa_brute(lib_path=None, n_obj=120, seed=21):
             assert np.all(ex["val"][0][outer] == 0) and np.all(pa["val"][0][outer] == 0), ("R2", kind)
 
 
+# ------------------------------------------------------------ polygon filling
+def _ring(z, x, y, pts):
+    """Closed ring of tile-local px vertices -> edges (k, 4) normalised."""
+    X, Y = _px_to_merc(z, x, y, np.array([p[0] for p in pts]), np.array([p[1] for p in pts]))
+    return np.stack([X, Y, np.roll(X, -1), np.roll(Y, -1)], 1)
+
+
+def _polys(z, x, y, rings_per_poly):
+    edges, first = [], [0]
+    for rings in rings_per_poly:
+        for ring in rings:
+            edges.append(_ring(z, x, y, ring))
+        first.append(first[-1] + sum(len(r) for r in rings))
+    return np.concatenate(edges), np.array(first)
+
+
+def _fill(edges, first, tiles, lib_path=None):
+    return oracle.OraclePolygons(edges, first, merc01=True, lib_path=lib_path).render(tiles)
+
+
+def _box(u0, v0, u1, v1):
+    return [(u0, v0), (u1, v0), (u1, v1), (u0, v1)]
+
+
+def pin_fill_closed_forms(lib_path=None):
+    """Squares, a hole, a separate polygon over the hole, a right triangle."""
+    z, x, y = 9, 300, 200
+    t = [[z, x, y]]
+    # square [10.25, 20.75] x [30.25, 40.75]: centres 10.5..20.5 and 30.5..40.5
+    e, f = _polys(z, x, y, [[_box(10.25, 30.25, 20.75, 40.75)]])
+    o = _fill(e, f, t, lib_path)
+    assert int((o["tri"] == 1).sum()) == 121 and not (o["tri"] == 2).any(), "square"
+    assert o["bit"][0, 35, 15] == 1 and o["bit"][0, 41, 15] == 0 and o["bit"][0, 35, 9] == 0, "square addressing"
+    # the same square with a hole [13.25, 16.75]^2 + 20 as a second ring
+    hole = _box(13.25, 33.25, 16.75, 36.75)
+    e, f = _polys(z, x, y, [[_box(10.25, 30.25, 20.75, 40.75), hole]])
+    o = _fill(e, f, t, lib_path)
+    assert int((o["tri"] == 1).sum()) == 121 - 16 and o["bit"][0, 35, 15] == 0, "hole (one polygon, two rings)"
+    # the hole as a polygon of its own lies inside the square: still filled
+    e, f = _polys(z, x, y, [[_box(10.25, 30.25, 20.75, 40.75)], [hole]])
+    o = _fill(e, f, t, lib_path)
+    assert int((o["tri"] == 1).sum()) == 121, "union over polygons"
+    # right triangle (100,100) (100+L,100) (100,100+L): centres with
+    # (i+.5-100) + (j+.5-100) < L inside, = L on the hypotenuse (ambiguous)
+    L = 37
+    e, f = _polys(z, x, y, [[[(100.0, 100.0), (100.0 + L, 100.0), (100.0, 100.0 + L)]]])
+    o = _fill(e, f, t, lib_path)
+    assert int((o["tri"] == 1).sum()) == L * (L - 1) // 2, "triangle interior"
+    assert int((o["tri"] == 2).sum()) == L, "triangle hypotenuse centres"
+    # orientation and a vertex exactly on a row of centres (half-open rule)
+    e, f = _polys(z, x, y, [[[(50.5, 60.0), (70.5, 80.5), (50.5, 101.0), (30.5, 80.5)]]])
+    o1 = _fill(e, f, t, lib_path)
+    e2 = e[::-1][:, [2, 3, 0, 1]]
+    o2 = _fill(e2, f, t, lib_path)
+    assert np.array_equal(o1["tri"], o2["tri"]), "orientation"
+    assert o1["bit"][0, 80, 50] == 1 and o1["tri"][0, 80, 50] == 1, "diamond centre"
+
+
+def _star_polys(rng, z, x, y, n_poly, spread=40.0):
+    rings = []
+    for _ in range(n_poly):
+        c = rng.uniform(-spread, 256 + spread, 2)
+        k = int(rng.integers(4, 25))
+        rho = rng.uniform(3.0, 60.0)
+        ang = np.sort(rng.uniform(0, 2 * np.pi, k))
+        rad = rho * rng.uniform(0.5, 1.0, k)
+        rings.append([[(c[0] + rad[q] * np.cos(ang[q]), c[1] + rad[q] * np.sin(ang[q])) for q in range(k)]])
+    return _polys(z, x, y, rings)
+
+
+def pin_fill_brute(lib_path=None, seed=31):
+    """Random star polygons against a numpy crossing count towards -x."""
+    rng = np.random.default_rng(seed)
+    for (z, x, y), n_poly in (((4, 3, 5), 12), ((11, 900, 700), 30), ((17, 60000, 50000), 8)):
+        e, f = _star_polys(rng, z, x, y, n_poly)
+        o = _fill(e, f, [[z, x, y]], lib_path)
+        inside, dist = brute_fill(e, f, z, x, y)
+        ok = dist > 1e-6 + 1e-9
+        assert np.array_equal(o["tri"][0][ok].astype(bool), inside[ok]), ("fill brute", z)
+        assert np.all(o["tri"][0][~ok] == 2) or np.all(inside[~ok] | (o["tri"][0][~ok] != 1)), ("fill band", z)
+
+
+def pin_fill_invariants(lib_path=None, seed=37):
+    """Reversed edges, cut edges (Algorithm 2's segment cutting must not
+    matter), permuted edges and polygons, tile translation."""
+    rng = np.random.default_rng(seed)
+    z, x, y = 10, 500, 400
+    e, f = _star_polys(rng, z, x, y, 20)
+    t = [[z, x, y]]
+    base = _fill(e, f, t, lib_path)["tri"]
+    rev = e[:, [2, 3, 0, 1]]
+    assert np.array_equal(_fill(rev, f, t, lib_path)["tri"], base), "reversed edges"
+    mid = 0.5 * (e[:, :2] + e[:, 2:])
+    cut = np.empty((2 * len(e), 4))
+    cut[0::2] = np.concatenate([e[:, :2], mid], 1)
+    cut[1::2] = np.concatenate([mid, e[:, 2:]], 1)
+    assert np.array_equal(_fill(cut, 2 * f, t, lib_path)["tri"], base), "cut edges"
+    perm_e = np.concatenate([e[f[p]:f[p + 1]][rng.permutation(f[p + 1] - f[p])] for p in range(len(f) - 1)])
+    assert np.array_equal(_fill(perm_e, f, t, lib_path)["tri"], base), "edges permuted within a polygon"
+    order = rng.permutation(len(f) - 1)
+    pe = np.concatenate([e[f[p]:f[p + 1]] for p in order])
+    pf = np.concatenate([[0], np.cumsum([f[p + 1] - f[p] for p in order])])
+    assert np.array_equal(_fill(pe, pf, t, lib_path)["tri"], base), "polygons permuted"
+    sh = e.copy()
+    S = 256.0 * 2 ** z
+    sh[:, 0] += 256.0 / S
+    sh[:, 2] += 256.0 / S
+    assert np.array_equal(_fill(sh, f, [[z, x + 1, y]], lib_path)["tri"], base), "translation"
+
+
 PINS = {
     "projection": pin_projection,
     "addressing": pin_addressing,
@@ -418,4 +528,7 @@ PINS = {
     "aa_lattice": pin_aa_lattice,
     "aa_ties_and_paper": pin_aa_ties_and_paper,
     "aa_brute": pin_aa_brute,
+    "fill_closed_forms": pin_fill_closed_forms,
+    "fill_brute": pin_fill_brute,
+    "fill_invariants": pin_fill_invariants,
 }

@@ -41,6 +41,12 @@ MUTANTS = [
     ("aa-inner-box", "h = sqrt(2.0) / 2.0 * R1;", "h = sqrt(2.0) * R1;"),
     ("aa-not-nearest", "if (d < D || (d == D && k < best)) {", "if (best < 0 || k < best) {"),
     ("aa-transposed", "const size_t p = (size_t)(256 * j + i);", "const size_t p = (size_t)(256 * i + j);"),
+    ("fill-closed-rule", "if ((ay > cy) != (by > cy)) {\n                            double ax",
+     "if ((ay >= cy) != (by > cy)) {\n                            double ax"),
+    ("fill-ray-side", "if (x > cx) par ^= 1;", "if (x > cx - 1.0) par ^= 1;"),
+    ("fill-first-polygon-only", "for (int32_t c = 0; c < M->count[nd] && !inside_sure; ++c) {",
+     "for (int32_t c = 0; c < M->count[nd] && c < 1; ++c) {"),
+    ("fill-box-min-y", "y0 = fmin(y0, fmin(P->ay[q], P->by[q]));", "y0 = fmin(y0, fmax(P->ay[q], P->by[q]));"),
 ]
 
 
@@ -53,5 +59,6 @@ def test_mutant_is_caught(name, old, new, tmp_path):
     sys.path.insert(0, ROOT)
     from oracle import build as ob
     lib = ob.build(str(mut), str(tmp_path / "libmut.so"))
-    res = subprocess.run([sys.executable, RUNNER, lib], capture_output=True, text=True, timeout=300)
+    family = name.split("-")[0] + "_" if name.startswith(("aa-", "fill-")) else ""
+    res = subprocess.run([sys.executable, RUNNER, lib, family], capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"planted mistake {name!r} was not caught:\n{res.stdout}{res.stderr}"
