@@ -54,6 +54,7 @@ WORKLOADS = {
     "c3": dict(name="points-1e9-clustered-10000tiles-z0-18-r1-3", kind=0),
     "c4": dict(name="polygon-edges-2e8-4096mixed-z2-20-w1-5", kind=2),
     "c5": dict(name="serving-linestrings-10M+points-1e9-poisson-1k-50k", kind=-1),
+    "c4fill": dict(name="polygon-fill-2e8edges-4096mixed-z2-20", kind=-2),
 }
 RATES = (1000.0, 2000.0, 5000.0, 10000.0, 20000.0, 50000.0)
 
@@ -223,6 +224,93 @@ def serve_bench(args, hv, torch):
     print(json.dumps(rec))
 
 
+def fill_bench(args, hv, torch):
+    """Polygon filling (SIBF) of the c4 polygons over the c4 requests."""
+    import oracle
+    stage("workload c4fill: generating")
+    edges = hvgen.gen_c4_edges(min_edges=int(200_000_000 * args.scale))
+    first = hvgen.c4_polygon_first(edges)
+    tiles, _ = hvgen.c4_requests(edges, n=4096)
+    n = len(tiles)
+    d = torch.from_numpy(edges).cuda()
+    torch.cuda.synchronize()
+    h = hv.hv_polygon_index_build(d, first)
+    del d
+    torch.cuda.empty_cache()
+    info = hv.hv_index_info(h)
+    stage(f"polygon index: {len(first) - 1} polygons, {edges.shape[0]} edges, {info['build_ms']:.1f} ms")
+    launch = json.loads(args.launch) if args.launch else None
+    out = torch.empty((n, hv.HV_MASK_BYTES), dtype=torch.uint8, device="cuda")
+    t4 = hv.tiles_array(tiles)
+    for _ in range(args.warmup):
+        hv.hv_render_fill(h, t4, out, launch)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record()
+        hv.hv_render_fill(h, t4, out, launch)
+        evs[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    value = n * args.steps / wall
+    stage(f"timed {args.steps} steps: {wall / args.steps * 1e3:.3f} ms/step")
+    per_tile = None
+    if not args.no_per_tile:
+        pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        for k in range(n):
+            pe[k][0].record()
+            hv.hv_render_fill(h, t4[k:k + 1], out[k], launch)
+            pe[k][1].record()
+        torch.cuda.synchronize()
+        lat = [a.elapsed_time(b) for a, b in pe]
+        per_tile = {"tiles_per_s": n / (time.perf_counter() - q0), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                    "launches": n}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the polygons near 64 requests at zoom >= 8 (a host index over all of
+        # them is out of reach here)
+        order = np.random.default_rng(12345).permutation(n)
+        sample = order[tiles[order, 0] >= 8][:64]
+        X, Y = oracle.project(edges[first[:-1], 0:2])
+        cell = np.minimum((Y * 256).astype(np.int64), 255) * 256 + np.minimum((X * 256).astype(np.int64), 255)
+        need = set()
+        for t in sample:
+            z, x, y = (int(v) for v in tiles[t])
+            cx, cy = x >> (z - 8), y >> (z - 8)
+            need.update(yy * 256 + xx for yy in range(max(0, cy - 1), min(255, cy + 1) + 1)
+                        for xx in range(max(0, cx - 1), min(255, cx + 1) + 1))
+        keep = np.nonzero(np.isin(cell, np.fromiter(need, dtype=np.int64)))[0]
+        sub_e = np.concatenate([edges[first[p]:first[p + 1]] for p in keep]) if len(keep) else np.zeros((0, 4))
+        sub_f = np.concatenate([[0], np.cumsum(first[keep + 1] - first[keep])]).astype(np.int64)
+        stage(f"oracle baseline: {len(keep)} polygons near the sampled requests")
+        P = oracle.OraclePolygons(sub_e, sub_f)
+        th = oracle.default_threads()
+        done, c0 = 0, time.perf_counter()
+        while done < len(sample) and time.perf_counter() - c0 < args.cpu_seconds:
+            P.render(tiles[sample[done:done + th]], nthreads=th)
+            done += len(sample[done:done + th])
+        dt = time.perf_counter() - c0
+        cpu = {"value": done / dt, "unit": "tiles/s", "cores": th, "kind": "oracle",
+               "sample": f"{done} requests at zoom >= 8 drawn at random (seed 12345) from the {n}, {dt:.1f} s of "
+                         f"CPU work on {th} threads; index over the {len(keep)} polygons whose first vertex lies "
+                         "within one zoom-8 cell of them; index build untimed"}
+    hv.hv_free(h)
+    rec = {
+        "metric": METRIC, "value": value, "unit": "tiles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4fill"]["name"], "n_edges": int(edges.shape[0]),
+                   "n_polygons": int(len(first) - 1), "zooms": "2-20", "requests_per_launch": n, "launch": launch},
+        "fill": {"tiles_per_s": value, "step_p50_ms": pct(step_ms, 50), "step_p99_ms": pct(step_ms, 99)},
+        "per_tile_launch": per_tile, "build_ms": info["build_ms"], "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec))
+
+
 class _Subset:
     """Serves a few requests of an executor once (warm-up)."""
 
@@ -275,6 +363,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c5":
         return serve_bench(args, hv, torch)
+    if args.workload == "c4fill":
+        return fill_bench(args, hv, torch)
     wl = WORKLOADS[args.workload]
     stage(f"workload {args.workload}: generating")
     objs, tiles, rr, cfg = make_workload(args.workload, args.scale)

@@ -278,6 +278,20 @@ def gen_c4_edges(seed: int = 4, min_edges: int = 200_000_000, n_centres: int = 2
     return np.concatenate(parts, axis=0)
 
 
+def c4_polygon_first(edges: np.ndarray) -> np.ndarray:
+    """Polygon offsets of a c4 edge set (npoly + 1 entries): polygons are
+    emitted whole, their edges consecutive, so a new polygon starts where an
+    edge does not begin at the previous edge's end.  Checks that every
+    polygon closes."""
+    e = np.asarray(edges, dtype=np.float64).reshape(-1, 4)
+    brk = np.nonzero(np.any(e[1:, 0:2] != e[:-1, 2:4], axis=1))[0] + 1
+    first = np.concatenate([[0], brk, [e.shape[0]]]).astype(np.int64)
+    closes = np.all(e[first[1:] - 1, 2:4] == e[first[:-1], 0:2], axis=1)
+    if not closes.all() or np.any(np.diff(first) < 3):
+        raise ValueError("edges do not form closed polygons of three or more edges")
+    return first
+
+
 def c4_requests(edges: np.ndarray, n: int = 4096, seed: int = 40, zlo: int = 2, zhi: int = 20):
     """Mixed requests: z ~ U{2..20}, anchor = a random vertex, width
     w ~ U{1..5} px -> half-width r = w/2.  Returns (tiles, r)."""

@@ -45,6 +45,8 @@ enum {
     HV_POINTS = 0,
     HV_SEGMENTS = 1,
     HV_POLYGON_EDGES = 2,
+    /* A polygon index for filling (hv_polygon_index_build, hv_render_fill). */
+    HV_POLYGONS = 3,
     /* OR-ed into kind: inputs are already normalised Mercator X,Y. */
     HV_INPUT_MERC01 = 0x100
 };
@@ -247,6 +249,33 @@ int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
  * calling thread's stream.  Errors as hv_render_batch, plus HV_EINVAL for
  * z = HV_MAX_ZOOM; nothing is launched on error. */
 int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch);
+
+/* Polygon index for filling (Sec. 3.1, the multi-level index for polygons:
+ * the polygons' bounding boxes in a tree -- the paper's RtreeMBR -- and each
+ * polygon's edges).  edges: device, n x 4 doubles (lon0, lat0, lon1, lat1,
+ * or normalised Mercator with flags = HV_INPUT_MERC01), grouped by polygon:
+ * polygon p owns edges first[p] .. first[p + 1] - 1, which must form closed
+ * rings (several rings make holes, even-odd).  first: host, npoly + 1
+ * entries, first[0] = 0, first[npoly] = n, at least 3 edges per polygon.
+ * Edges are copied; the caller keeps ownership of both arrays.  Synchronous.
+ * Returns NULL on error (hv_last_error): HV_EINVAL for a bad first[], NULL
+ * pointers, host edges, or a coordinate that is not finite or outside
+ * [-180, 180] x [-90, 90]; HV_ENOMEM / HV_EHIP as hv_index_build.  npoly = 0
+ * gives an empty index (all masks zero).  hv_info reports kind HV_POLYGONS
+ * and n = npoly. */
+hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *first, int64_t npoly, int flags);
+
+/* Fill masks (SIBF, Sec. 3.2.2, Algorithm 2): pixel (i, j) is set when its
+ * centre lies inside some polygon of the index, by the even-odd rule (an
+ * edge counts when exactly one endpoint lies below the centre's row line, so
+ * vertices on the line count once and edges parallel to x never).  tiles,
+ * out_masks as for hv_render_tiles (8192 bytes per tile, same bit layout).
+ * launch: region mode only (region 32 or 64; NULL = the default shape).
+ * Errors as hv_render_tiles_ex, plus HV_EINVAL for an index that is not a
+ * polygon index or a launch with region 0.  The distance-mask entry points
+ * reject polygon indexes. */
+int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
+                   const hv_launch *launch);
 
 /* Kernel timing for roofline figures.  Renders the batch reps times, as
  * hv_render_batch would (same arguments; launch NULL takes the tuned shape

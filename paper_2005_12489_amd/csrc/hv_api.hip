@@ -50,6 +50,10 @@ hv::DevIndex dev_view(const hv_index *ix) {
     d.n = ix->a.n;
     d.levels = ix->a.levels;
     d.seg = ix->a.seg;
+    d.order = ix->a.order;
+    d.pedges = ix->p.edges;
+    d.pfirst = ix->p.first;
+    d.npoly = ix->p.npoly;
     return d;
 }
 
@@ -205,6 +209,8 @@ int plan_batch(const hv_request *reqs, int64_t n, BatchPlan *p) {
     for (int64_t k = 0; k < n; ++k) {
         const hv_request &q = reqs[k];
         if (!q.index) return fail(HV_EINVAL, "request " + std::to_string(k) + ": index is NULL");
+        if (q.index->kind == HV_POLYGONS)
+            return fail(HV_EINVAL, "request " + std::to_string(k) + ": a polygon index renders with hv_render_fill");
         int rc = validate_tile(q.z, q.x, q.y, k);
         if (rc) return rc;
         if ((rc = validate_r(q.r_px, k))) return rc;
@@ -341,12 +347,119 @@ hv_index *hv_index_build(const double *objects, int kind, int64_t n) {
 void hv_free(hv_index *index) {
     if (!index) return;
     hv::free_index_arrays(&index->a);
+    hv::free_poly_arrays(&index->p);
     delete index;
+}
+
+hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *first, int64_t npoly, int flags) {
+    if ((flags & ~HV_INPUT_MERC01) != 0) {
+        fail(HV_EINVAL, "flags must be 0 or HV_INPUT_MERC01");
+        return nullptr;
+    }
+    if (n < 0 || n > HV_MAX_OBJECTS || npoly < 0 || npoly > n / 3) {
+        fail(HV_EINVAL, "n outside [0, 2e9] or npoly outside [0, n / 3]");
+        return nullptr;
+    }
+    if (npoly > 0 && (!edges || !first)) {
+        fail(HV_EINVAL, "edges or first is NULL");
+        return nullptr;
+    }
+    if (npoly == 0 && n != 0) {
+        fail(HV_EINVAL, "edges without polygons");
+        return nullptr;
+    }
+    for (int64_t p = 0; p < npoly; ++p) {
+        if ((p == 0 && first[0] != 0) || first[p + 1] - first[p] < 3) {
+            fail(HV_EINVAL, "polygon " + std::to_string(p) + ": first[0] must be 0 and a polygon needs >= 3 edges");
+            return nullptr;
+        }
+    }
+    if (npoly > 0 && first[npoly] != n) {
+        fail(HV_EINVAL, "first[npoly] must equal n");
+        return nullptr;
+    }
+    if (n > 0 && !is_device_pointer(edges)) {
+        fail(HV_EINVAL, "edges must be device memory");
+        return nullptr;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    hv_index *ix = new (std::nothrow) hv_index;
+    if (!ix) {
+        fail(HV_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    ix->kind = HV_POLYGONS;
+    if (npoly == 0) {
+        ix->device = -1;
+        t_err.clear();
+        return ix;
+    }
+    if (hipGetDevice(&ix->device) != hipSuccess) {
+        hip_status(hipGetLastError(), "hipGetDevice");
+        delete ix;
+        return nullptr;
+    }
+    const hv::BuildResult br = hv::build_polygons(edges, n, first, npoly, flags, t_stream, &ix->a, &ix->p);
+    if (br.status != HV_OK) {
+        fail(br.status, std::string("hv_polygon_index_build: ") + br.msg);
+        hv::free_index_arrays(&ix->a);
+        hv::free_poly_arrays(&ix->p);
+        delete ix;
+        return nullptr;
+    }
+    if (ix->a.levels > 0) {
+        double4 rb;
+        const hipError_t e = hipMemcpy(&rb, ix->a.nodes + ix->a.level_off[ix->a.levels - 1], sizeof rb,
+                                       hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            hip_status(e, "hv_polygon_index_build");
+            hv_free(ix);
+            return nullptr;
+        }
+        ix->root[0] = rb.x; ix->root[1] = rb.y; ix->root[2] = rb.z; ix->root[3] = rb.w;
+    }
+    ix->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    t_err.clear();
+    return ix;
+}
+
+int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
+                   const hv_launch *launch) {
+    if (!index) return fail(HV_EINVAL, "index is NULL");
+    if (index->kind != HV_POLYGONS) return fail(HV_EINVAL, "hv_render_fill needs a polygon index");
+    if (n_tiles < 0) return fail(HV_EINVAL, "n_tiles < 0");
+    if (n_tiles > 0 && (!tiles || !out_masks)) return fail(HV_EINVAL, "tiles or out_masks is NULL");
+    int rc = validate_tiles(tiles, n_tiles);
+    if (rc) return rc;
+    hv::LaunchShape shape;
+    if ((rc = resolve_shape(launch, index->a.levels, &shape))) return rc;
+    if (shape.region == 0) return fail(HV_EINVAL, "filling runs in region mode: launch.region must be 32 or 64");
+    shape.fill = 1;
+    if (hv::query_lds_bytes(shape, index->a.levels) > 65536)
+        return fail(HV_EINVAL, "launch shape needs more than 64 KiB of LDS per workgroup");
+    if (n_tiles == 0) {
+        t_err.clear();
+        return HV_OK;
+    }
+    if ((rc = validate_out(out_masks))) return rc;
+    if (index->device >= 0) {
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess) return hip_status(hipGetLastError(), "hipGetDevice");
+        if (dev != index->device) return fail(HV_EINVAL, "the index lives on another device");
+    }
+    std::vector<hv::DevReq> reqs((size_t)n_tiles);
+    for (int64_t k = 0; k < n_tiles; ++k) reqs[(size_t)k] = hv::DevReq{tiles[k].z, tiles[k].x, tiles[k].y, 0, 0.0};
+    const hv::DevIndex dv = dev_view(index);
+    rc = run_batch(&dv, 1, index->a.levels, reqs.data(), n_tiles, out_masks, shape, "hv_render_fill");
+    if (rc) return rc;
+    t_err.clear();
+    return HV_OK;
 }
 
 int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, const hv_style *style,
                        uint8_t *out_masks, const hv_launch *launch) {
     if (!index) return fail(HV_EINVAL, "index is NULL");
+    if (index->kind == HV_POLYGONS) return fail(HV_EINVAL, "a polygon index renders with hv_render_fill");
     if (n_tiles < 0) return fail(HV_EINVAL, "n_tiles < 0");
     int rc = validate_style(style);
     if (rc) return rc;

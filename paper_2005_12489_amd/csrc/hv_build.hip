@@ -92,6 +92,44 @@ __global__ __launch_bounds__(256) void k_project_key(const double *__restrict__ 
     ids[i] = (uint32_t)i;
 }
 
+// Projects polygon edges (4 doubles each) in their given order; flags
+// coordinates that are not finite or outside [-180, 180] x [-90, 90].
+__global__ __launch_bounds__(256) void k_project_edges(const double *__restrict__ in, int64_t n, int merc,
+                                                       double *__restrict__ out, int *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = in[i * 4 + c];
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bad |= !isfinite(v[c]);
+    if (!merc) bad |= fabs(v[0]) > 180.0 || fabs(v[1]) > 90.0 || fabs(v[2]) > 180.0 || fabs(v[3]) > 90.0;
+    if (bad) atomicOr(err, 1);
+    double p[4] = {v[0], v[1], v[2], v[3]};
+    if (!merc) {
+        mercator(v[0], v[1], p[0], p[1]);
+        mercator(v[2], v[3], p[2], p[3]);
+    }
+    reinterpret_cast<double4 *>(out)[i] = make_double4(p[0], p[1], p[2], p[3]);
+}
+
+// Bounding box of each polygon's edges, written as the diagonal segment
+// (min X, min Y) - (max X, max Y), whose own box is the polygon's box.
+__global__ __launch_bounds__(256) void k_polygon_boxes(const double *__restrict__ edges,
+                                                       const int64_t *__restrict__ first, int64_t npoly,
+                                                       double *__restrict__ diag) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npoly) return;
+    double x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+    for (int64_t e = first[p]; e < first[p + 1]; ++e) {
+        const double4 g = reinterpret_cast<const double4 *>(edges)[e];
+        x0 = fmin(x0, fmin(g.x, g.z)); x1 = fmax(x1, fmax(g.x, g.z));
+        y0 = fmin(y0, fmin(g.y, g.w)); y1 = fmax(y1, fmax(g.y, g.w));
+    }
+    reinterpret_cast<double4 *>(diag)[p] = make_double4(x0, y0, x1, y1);
+}
+
 // ------------------------------------------------------------ scans
 __device__ inline uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -321,6 +359,61 @@ BuildResult hip_fail(hipError_t e) {
 }
 
 }  // namespace
+
+void free_poly_arrays(PolyArrays *p) {
+    if (p->edges) (void)hipFree(p->edges);
+    if (p->first) (void)hipFree(p->first);
+    p->edges = nullptr;
+    p->first = nullptr;
+}
+
+BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first, int64_t npoly, int flags,
+                           hipStream_t st, IndexArrays *tree, PolyArrays *poly) {
+    const int merc = (flags & HV_INPUT_MERC01) != 0;
+    poly->npoly = npoly;
+    poly->n_edges = n;
+    tree->n = 0;
+    tree->seg = 1;
+    tree->levels = 0;
+    if (npoly == 0) return {HV_OK, ""};
+    double *diag = nullptr;
+    int *err = nullptr;
+    auto bail = [&](hipError_t e) {
+        if (diag) (void)hipFree(diag);
+        if (err) (void)hipFree(err);
+        free_poly_arrays(poly);
+        return hip_fail(e);
+    };
+    hipError_t e;
+    if ((e = hipMalloc((void **)&poly->edges, sizeof(double) * 4 * (size_t)n)) != hipSuccess) return bail(e);
+    if ((e = hipMalloc((void **)&poly->first, sizeof(int64_t) * (size_t)(npoly + 1))) != hipSuccess) return bail(e);
+    if ((e = hipMalloc((void **)&diag, sizeof(double) * 4 * (size_t)npoly)) != hipSuccess) return bail(e);
+    if ((e = hipMalloc((void **)&err, sizeof(int))) != hipSuccess) return bail(e);
+    if ((e = hipMemcpyAsync(poly->first, first, sizeof(int64_t) * (size_t)(npoly + 1), hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
+        return bail(e);
+    if ((e = hipMemsetAsync(err, 0, sizeof(int), st)) != hipSuccess) return bail(e);
+    hipLaunchKernelGGL(k_project_edges, dim3((uint32_t)cdiv(n, 256)), dim3(256), 0, st, edges, n, merc, poly->edges,
+                       err);
+    hipLaunchKernelGGL(k_polygon_boxes, dim3((uint32_t)cdiv(npoly, 256)), dim3(256), 0, st, poly->edges, poly->first,
+                       npoly, diag);
+    if ((e = hipGetLastError()) != hipSuccess) return bail(e);
+    int herr = 0;
+    if ((e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return bail(e);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e);
+    if (herr) {
+        (void)hipFree(diag);
+        (void)hipFree(err);
+        free_poly_arrays(poly);
+        return {HV_EINVAL, "edges hold a non-finite coordinate, |lon| > 180 or |lat| > 90"};
+    }
+    const BuildResult r = build_index(diag, HV_SEGMENTS | HV_INPUT_MERC01, npoly, st, tree);
+    (void)hipFree(diag);
+    (void)hipFree(err);
+    if (r.status != HV_OK) free_poly_arrays(poly);
+    else tree->device_bytes += (int64_t)(sizeof(double) * 4 * (size_t)n + sizeof(int64_t) * (size_t)(npoly + 1));
+    return r;
+}
 
 void free_index_arrays(IndexArrays *a) {
     if (a->obj) (void)hipFree(a->obj);

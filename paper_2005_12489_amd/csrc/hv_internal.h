@@ -24,6 +24,12 @@ struct DevIndex {
     int64_t n;
     int32_t levels;
     int32_t seg;                 // 0 points, 1 segments / edges
+    // polygon indexes only (filling): the tree above holds the polygons'
+    // bounding boxes as diagonals, in sorted order
+    const uint32_t *order;       // sorted position -> polygon
+    const double *pedges;        // edges in polygon order, 4 doubles each
+    const int64_t *pfirst;       // polygon p owns edges [pfirst[p], pfirst[p + 1])
+    int64_t npoly;
 };
 
 // A request as the kernels see it: one tile of one index with its own
@@ -54,6 +60,22 @@ struct IndexArrays {
     int64_t device_bytes = 0;
 };
 
+// Device arrays of a polygon index beyond its box tree (freed by
+// free_poly_arrays).
+struct PolyArrays {
+    double *edges = nullptr;     // projected, polygon order
+    int64_t *first = nullptr;    // npoly + 1
+    int64_t npoly = 0, n_edges = 0;
+};
+
+// Builds a polygon index: projects `edges` (device, n x 4 lon0, lat0, lon1,
+// lat1, or normalised with HV_INPUT_MERC01 in flags) in their given order,
+// copies `first` (host, npoly + 1), computes each polygon's bounding box and
+// builds the Hilbert R-tree over those boxes (as diagonal segments).
+BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first, int64_t npoly, int flags,
+                           hipStream_t stream, IndexArrays *tree, PolyArrays *poly);
+void free_poly_arrays(PolyArrays *p);
+
 // Builds the index on `stream` and synchronises.  `objects` is a device
 // pointer; validation of coordinates happens on the device.
 BuildResult build_index(const double *objects, int kind_flags, int64_t n, hipStream_t stream,
@@ -67,6 +89,7 @@ struct LaunchShape {
     int grid;         // workgroups of the persistent query kernel (0: fill the GPU)
     int region;       // 0: one wave per block; 32 or 64: one workgroup per region of that side
     int opl;          // region mode: objects loaded per lane at a leaf step (1, 2 or 4)
+    int fill = 0;     // 1: polygon filling (region mode) instead of the distance masks
 };
 
 // LDS bytes per workgroup for a shape and the deepest index of a batch.
@@ -131,6 +154,7 @@ int persistent_grid(const LaunchShape &s, int max_levels);
 // An index as the C ABI hands it out.
 struct hv_index {
     hv::IndexArrays a;
+    hv::PolyArrays p;   // polygon indexes only
     int kind = 0;
     int device = 0;     // -1 for an empty index (no device memory)
     double root[4] = {0, 0, 0, 0};

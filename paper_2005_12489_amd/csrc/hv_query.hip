@@ -920,6 +920,192 @@ __global__ __launch_bounds__(256) void k_query_region(DevBatch B, int cap, int m
     }
 }
 
+// ------------------------------------------------------------ polygon filling
+// SIBF (Algorithm 2) per region of RS x RS pixels.  The index's tree holds
+// the polygons' bounding boxes; the walk collects the polygons whose box
+// meets the region's pixel centres (Algorithm 2's RtreeMBR query).  For
+// each, every edge toggles, in every region row whose centre line it
+// crosses (half-open in y: an edge is crossed when exactly one endpoint lies
+// below the line, so a vertex on it counts once and edges parallel to x
+// never, which is what IsLevel and segment cutting achieve in the paper),
+// the pixels whose centre lies right of the crossing.  After all its edges a
+// pixel's bit is the parity of the crossings left of it: inside that polygon
+// (even-odd rule, holes included).  The fill is the OR over polygons.
+// Casting the ray towards -x instead of towards the nearer side of the box
+// gives the same parity for closed rings.
+struct FillLds {
+    uint32_t *stk;
+    uint32_t *cand;  // candidate polygons
+    uint32_t *mask;  // RS rows x RS/32 words: filled so far
+    uint32_t *par;   // parity rows of the polygon being tested
+    int *ctl;        // [0] stack size, [1] candidates
+};
+
+__host__ __device__ inline size_t fill_lds_bytes(int cap, int levels, int threads, int rs) {
+    return align16((size_t)region_stack_words(levels, threads) * 4) + align16((size_t)cap * 4) +
+           2 * align16((size_t)rs * (rs / 32) * 4) + 16;
+}
+
+template <int RS>
+__device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq, int64_t t, int reg,
+                                           const uint32_t *__restrict__ frontier, const int32_t *__restrict__ fmeta,
+                                           uint8_t *__restrict__ out, int cap, const FillLds &L) {
+    constexpr int NR = 256 / RS;
+    constexpr int W = RS / 32;
+    const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
+    uint32_t *stk = L.stk, *mask = L.mask, *par = L.par;
+    int *ctl = L.ctl;
+    const int rx = reg % NR, ry = reg / NR;
+    const double S = ldexp(256.0, rq.z), iS = ldexp(1.0, -8 - rq.z);
+    const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
+    const double i0 = (double)(rx * RS), j0 = (double)(ry * RS);
+    const double m = kCullPad;
+    const double qx0 = ((ox + i0) + (0.5 - m)) * iS, qx1 = ((ox + i0) + ((RS - 0.5) + m)) * iS;
+    const double qy0 = ((oy + j0) + (0.5 - m)) * iS, qy1 = ((oy + j0) + ((RS - 0.5) + m)) * iS;
+    uint8_t *tm = out + t * (int64_t)HV_MASK_BYTES;
+
+    const int4 fm = reinterpret_cast<const int4 *>(fmeta)[t];
+    const int fcount = fm.x, flevel = fm.y;
+    const uint64_t reach = (uint64_t)(uint32_t)fm.z | ((uint64_t)(uint32_t)fm.w << 32);
+    if (!((reach >> reg) & 1ull)) {
+        for (int k = tid; k < RS * W; k += nthr)
+            *reinterpret_cast<uint32_t *>(tm + (ry * RS + k / W) * 32 + rx * (RS / 8) + 4 * (k % W)) = 0u;
+        return;
+    }
+    for (int k = tid; k < RS * W; k += nthr) mask[k] = 0;
+    if (tid == 0) {
+        ctl[0] = 0;
+        ctl[1] = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < fcount; base += nthr) {
+        bool hit = false;
+        uint32_t node = 0;
+        if (base + tid < fcount) {
+            node = frontier[t * kFrontier + base + tid];
+            hit = meets(ix.nodes[ix.meta[flevel] + node], qx0, qx1, qy0, qy1);
+        }
+        const int pos = wave_alloc(&ctl[0], __ballot(hit), lane);
+        if (hit) stk[pos] = ((uint32_t)flevel << kLevelShift) | node;
+    }
+    __syncthreads();
+
+    // Tests the queued polygons one by one; true once the region is all filled.
+    auto test = [&]() -> bool {
+        const int nc = ctl[1];
+        for (int c = 0; c < nc; ++c) {
+            const int64_t pid = L.cand[c];
+            for (int k = tid; k < RS * W; k += nthr) par[k] = 0;
+            __syncthreads();
+            const int64_t e1 = ix.pfirst[pid + 1];
+            for (int64_t e = ix.pfirst[pid] + tid; e < e1; e += nthr) {
+                const double4 g = reinterpret_cast<const double4 *>(ix.pedges)[e];
+                const double ax = g.x * S - ox, ay = g.y * S - oy, bx = g.z * S - ox, by = g.w * S - oy;
+                if (ay == by || fmin(ax, bx) >= i0 + (RS - 0.5)) continue;  // no crossing left of a pixel
+                // candidate rows, one wider on each side; each is checked exactly
+                const int jlo = (int)fmax(ceil(fmin(ay, by) - j0 - 0.5) - 1.0, 0.0);
+                const int jhi = (int)fmin(ceil(fmax(ay, by) - j0 - 0.5), RS - 1.0);
+                for (int j = jlo; j <= jhi; ++j) {
+                    const double yc = j0 + (double)j + 0.5;
+                    if ((ay > yc) == (by > yc)) continue;
+                    const double xc = ax + (yc - ay) * (bx - ax) / (by - ay);
+                    const double f = floor(xc - i0 - 0.5) + 1.0;  // first pixel strictly right of xc
+                    if (f >= RS) continue;
+                    const int k0 = f <= 0.0 ? 0 : (int)f;
+                    for (int wd = k0 >> 5; wd < W; ++wd) {
+                        const int lo = k0 - 32 * wd;
+                        atomicXor(&par[j * W + wd], lo <= 0 ? 0xffffffffu : (0xffffffffu << lo));
+                    }
+                }
+            }
+            __syncthreads();
+            bool full = true;
+            for (int k = tid; k < RS * W; k += nthr) {
+                const uint32_t v = mask[k] | par[k];
+                mask[k] = v;
+                full &= v == 0xffffffffu;
+            }
+            if (__syncthreads_and(full)) return true;
+        }
+        if (tid == 0) ctl[1] = 0;
+        __syncthreads();
+        return false;
+    };
+
+    bool done = false;
+    for (;;) {
+        const int sp = ctl[0];
+        if (sp == 0) break;
+        const int lvl = (int)(stk[sp - 1] >> kLevelShift);
+        const int per_step = lvl > 0 ? nthr / kFan : nthr / kLeaf;
+        const bool top = tid < per_step && tid < sp && (int)(stk[sp - 1 - tid] >> kLevelShift) == lvl;
+        const int npop = __syncthreads_count(top);
+        const int j = tid >> 4, c = tid & 15;
+        const uint32_t node = j < npop ? (stk[sp - 1 - j] & kIdxMask) : 0u;
+        if (tid == 0) ctl[0] = sp - npop;
+        __syncthreads();
+        if (lvl > 0) {
+            const int cl = lvl - 1;
+            const int64_t child = (int64_t)node * kFan + c;
+            const bool push = j < npop && child < ix.meta[kMaxLevels + cl] &&
+                              meets(ix.nodes[ix.meta[cl] + child], qx0, qx1, qy0, qy1);
+            const int pos = wave_alloc(&ctl[0], __ballot(push), lane);
+            if (push) stk[pos] = ((uint32_t)cl << kLevelShift) | (uint32_t)child;
+        } else {
+            // a polygon whose box holds no pixel centre of the region holds none
+            const int64_t o = (int64_t)node * kLeaf + c;
+            bool keep = false;
+            if (j < npop && o < ix.n) {
+                const double4 bb = reinterpret_cast<const double4 *>(ix.obj)[o];
+                const double cx0 = fmax(ceil(bb.x * S - ox - i0 - 0.5), 0.0);
+                const double cx1 = fmin(floor(bb.z * S - ox - i0 - 0.5), RS - 1.0);
+                const double cy0 = fmax(ceil(bb.y * S - oy - j0 - 0.5), 0.0);
+                const double cy1 = fmin(floor(bb.w * S - oy - j0 - 0.5), RS - 1.0);
+                keep = cx0 <= cx1 && cy0 <= cy1;
+            }
+            const int slot = wave_alloc(&ctl[1], __ballot(keep), lane);
+            if (keep) L.cand[slot] = ix.order[o];
+        }
+        __syncthreads();
+        if (ctl[1] > cap - nthr && test()) {
+            done = true;
+            break;
+        }
+    }
+    if (!done && ctl[1] > 0) test();
+    __syncthreads();
+    for (int k = tid; k < RS * W; k += nthr) {
+        const int row = k / W, wd = k % W;
+        *reinterpret_cast<uint32_t *>(tm + (ry * RS + row) * 32 + rx * (RS / 8) + 4 * wd) = mask[k];
+    }
+    __syncthreads();
+}
+
+template <int RS>
+__global__ __launch_bounds__(256) void k_fill_region(DevBatch B, int cap, int max_levels) {
+    extern __shared__ double4 smem[];
+    constexpr int RPT = (256 / RS) * (256 / RS);
+    unsigned char *base = reinterpret_cast<unsigned char *>(smem);
+    FillLds L;
+    L.stk = reinterpret_cast<uint32_t *>(base);
+    unsigned char *cb = base + align16((size_t)region_stack_words(max_levels, blockDim.x) * 4);
+    L.cand = reinterpret_cast<uint32_t *>(cb);
+    L.mask = reinterpret_cast<uint32_t *>(cb + align16((size_t)cap * 4));
+    L.par = L.mask + align16((size_t)RS * (RS / 32) * 4) / 4;
+    L.ctl = reinterpret_cast<int *>(L.par + align16((size_t)RS * (RS / 32) * 4) / 4);
+    uint8_t *const out = B.hdr->out;
+    zero_empty_tiles(B, out);
+    const ItemMap im(B.hdr->counter, RPT);
+    for (int64_t u = im.first; u < im.n; u += im.step) {
+        const int64_t t = B.list[im.pos(u, RPT)];
+        const int reg = (int)(u % RPT);
+        const DevReq rq = B.reqs[t];
+        const DevIndex ix = B.ixs[rq.index];
+        fill_query<RS>(ix, rq, t, reg, B.frontier, B.fmeta, out, cap, L);
+        if (threadIdx.x == 0) part_done(B, t, RPT);
+    }
+}
+
 // ------------------------------------------------------------ anti-aliasing
 // Algorithm 1's value 0-4 per pixel counts the pixel's four sub-samples
 // (centre +- 1/4 px in x and y) within r.  Those sub-samples are exactly the
@@ -955,7 +1141,7 @@ RegionKernel region_kernel(const LaunchShape &s) {
 }
 
 struct GridKey {
-    int device, block, waves, region, opl;
+    int device, block, waves, region, opl, fill;
     size_t lds;
     int grid;
 };
@@ -963,6 +1149,7 @@ struct GridKey {
 }  // namespace
 
 size_t query_lds_bytes(const LaunchShape &s, int max_levels) {
+    if (s.fill) return fill_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region);
     if (s.region) return region_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region);
     return (size_t)s.waves * wave_lds_bytes(s.cand_cap, max_levels, s.block);
 }
@@ -1018,12 +1205,15 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
     std::lock_guard<std::mutex> g(mu);
     for (int k = 0; k < ncache; ++k)
         if (cache[k].device == dev && cache[k].block == s.block && cache[k].waves == s.waves &&
-            cache[k].region == s.region && cache[k].opl == s.opl && cache[k].lds == lds)
+            cache[k].region == s.region && cache[k].opl == s.opl && cache[k].fill == s.fill && cache[k].lds == lds)
             return cache[k].grid;
     int per_cu = 0, cus = 0;
     const int thr = 64 * s.waves;
     hipError_t e;
-    if (s.region) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, region_kernel(s), thr, lds);
+    if (s.fill)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, s.region == 64 ? k_fill_region<64> : k_fill_region<32>,
+                                                         thr, lds);
+    else if (s.region) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, region_kernel(s), thr, lds);
     else if (s.block == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<8>, thr, lds);
     else if (s.block == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<16>, thr, lds);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query<32>, thr, lds);
@@ -1033,7 +1223,7 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
     // ten times what fits at once: the dispatcher then hands out the
     // remaining workgroups as others finish, which evens out uneven blocks
     const int grid = 10 * per_cu * cus;
-    if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, s.region, s.opl, lds, grid};
+    if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, s.region, s.opl, s.fill, lds, grid};
     return grid;
 }
 
@@ -1062,7 +1252,9 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, 
     int64_t grid = s.grid > 0 ? s.grid : persistent_grid(s, max_levels);
     if (grid > need) grid = need;
     const dim3 g((uint32_t)grid), b((uint32_t)(64 * s.waves));
-    if (s.region) hipLaunchKernelGGL(region_kernel(s), g, b, lds, st, B, s.cand_cap, max_levels);
+    if (s.fill && s.region == 64) hipLaunchKernelGGL(k_fill_region<64>, g, b, lds, st, B, s.cand_cap, max_levels);
+    else if (s.fill) hipLaunchKernelGGL(k_fill_region<32>, g, b, lds, st, B, s.cand_cap, max_levels);
+    else if (s.region) hipLaunchKernelGGL(region_kernel(s), g, b, lds, st, B, s.cand_cap, max_levels);
     else if (s.block == 8) hipLaunchKernelGGL(k_query<8>, g, b, lds, st, B, s.cand_cap, max_levels);
     else if (s.block == 16) hipLaunchKernelGGL(k_query<16>, g, b, lds, st, B, s.cand_cap, max_levels);
     else hipLaunchKernelGGL(k_query<32>, g, b, lds, st, B, s.cand_cap, max_levels);

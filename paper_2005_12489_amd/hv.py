@@ -31,7 +31,7 @@ def _hip_runtimes() -> set:
     with open("/proc/self/maps") as f:
         return {ln.split()[-1] for ln in f if "libamdhip64" in ln and "/" in ln}
 
-HV_POINTS, HV_SEGMENTS, HV_POLYGON_EDGES = 0, 1, 2
+HV_POINTS, HV_SEGMENTS, HV_POLYGON_EDGES, HV_POLYGONS = 0, 1, 2, 3
 HV_INPUT_MERC01 = 0x100
 HV_OK, HV_EINVAL, HV_ENOMEM, HV_EHIP = 0, -1, -2, -3
 HV_READ_ORDER, HV_READ_OBJECTS, HV_READ_NODES = 0, 1, 2
@@ -42,7 +42,7 @@ HV_MAX_ZOOM = 22
 SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free", "hv_last_error",
            "hv_set_stream", "hv_index_info", "hv_index_read", "hv_render_batch", "hv_batcher_create",
            "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch",
-           "hv_time_kernels", "hv_render_batch_aa")
+           "hv_time_kernels", "hv_render_batch_aa", "hv_polygon_index_build", "hv_render_fill")
 
 # hv_request as a numpy record (32 bytes, the C layout)
 REQUEST_DTYPE = np.dtype([("index", np.uint64), ("z", np.int32), ("x", np.int32), ("y", np.int32),
@@ -114,6 +114,10 @@ lib.hv_autotune.restype = ctypes.c_int
 lib.hv_autotune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.POINTER(ctypes.c_double)]
 lib.hv_tuned_launch.restype = ctypes.c_int
 lib.hv_tuned_launch.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(hv_launch)]
+lib.hv_polygon_index_build.restype = _P
+lib.hv_polygon_index_build.argtypes = [_P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int]
+lib.hv_render_fill.restype = ctypes.c_int
+lib.hv_render_fill.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
 lib.hv_render_batch_aa.restype = ctypes.c_int
 lib.hv_render_batch_aa.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
 lib.hv_time_kernels.restype = ctypes.c_int
@@ -264,6 +268,29 @@ def hv_render_batch(reqs, out_masks, launch=None) -> None:
     _sync_stream()
     _check(lib.hv_render_batch(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks),
                                ctypes.byref(L) if L else None))
+
+
+def hv_polygon_index_build(edges, first, flags: int = 0) -> int:
+    """Polygon index from device edges (torch tensor (n, 4) float64) grouped
+    by polygon, first (host, npoly + 1 int64)."""
+    f = np.ascontiguousarray(first, dtype=np.int64)
+    n = int(f[-1]) if f.size else 0
+    if hasattr(edges, "dtype") and n > 0:
+        if str(edges.dtype) != "torch.float64" or not edges.is_contiguous() or tuple(edges.shape) != (n, 4):
+            raise HvError(HV_EINVAL, "edges must be a contiguous float64 tensor of shape (first[-1], 4)")
+    h = lib.hv_polygon_index_build(_device_ptr(edges), int(n), f.ctypes.data_as(_P) if f.size else None,
+                                   int(f.size - 1) if f.size else 0, int(flags))
+    if not h:
+        raise HvError(HV_EINVAL, hv_last_error())
+    return h
+
+
+def hv_render_fill(index: int, tiles, out_masks, launch=None) -> None:
+    t = tiles_array(tiles)
+    L = _launch(launch)
+    _sync_stream()
+    _check(lib.hv_render_fill(index, t.ctypes.data_as(_P), t.shape[0], _device_ptr(out_masks),
+                              ctypes.byref(L) if L else None))
 
 
 def hv_render_batch_aa(reqs, out_values, launch=None) -> None:

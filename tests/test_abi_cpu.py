@@ -123,3 +123,39 @@ def test_batch_validation_before_any_device_call(hv):
                 hv.hv_time_kernels(reqs, 1, reps=reps)
     finally:
         hv.hv_free(h)
+
+
+def test_polygon_index_validation_before_any_device_call(hv):
+    bad = [([1, 4], "first\\[0\\]"), ([0, 2], "npoly outside"), ([0, 2, 7], "3 edges"),
+           ([0, 3, 2, 9], "3 edges"), ([0, 3, 6], "device memory")]
+    for first, msg in bad:
+        with pytest.raises(hv.HvError, match=msg):
+            hv.hv_polygon_index_build(1, first)
+    with pytest.raises(hv.HvError, match="flags"):
+        hv.hv_polygon_index_build(1, [0, 3], flags=2)
+    with pytest.raises(hv.HvError, match="NULL"):
+        hv.hv_polygon_index_build(None, [0, 3])
+    host = np.zeros((3, 4))
+    with pytest.raises(hv.HvError, match="device memory"):
+        hv.hv_polygon_index_build(host.ctypes.data, [0, 3])
+    e = hv.hv_polygon_index_build(None, [0])            # no polygons: an empty index, no device memory
+    try:
+        info = hv.hv_index_info(e)
+        assert info["kind"] == hv.HV_POLYGONS and info["n"] == 0
+        with pytest.raises(hv.HvError, match="hv_render_fill"):
+            hv.hv_render_tiles(e, [(0, 0, 0)], 1.0, 1)
+        with pytest.raises(hv.HvError, match="hv_render_fill"):
+            hv.hv_render_batch(hv.requests(e, [(0, 0, 0)], 1.0), 1)
+        with pytest.raises(hv.HvError, match="region"):
+            hv.hv_render_fill(e, [(0, 0, 0)], 1, dict(region=0, block=16))
+        with pytest.raises(hv.HvError, match="zoom"):
+            hv.hv_render_fill(e, [(23, 0, 0)], 1)
+        hv.hv_render_fill(e, np.zeros((0, 3)), 0)      # nothing to render
+    finally:
+        hv.hv_free(e)
+    p = hv.hv_index_build(None, hv.HV_POINTS, 0)
+    try:
+        with pytest.raises(hv.HvError, match="polygon index"):
+            hv.hv_render_fill(p, [(0, 0, 0)], 1)
+    finally:
+        hv.hv_free(p)
