@@ -384,7 +384,7 @@ def main():
     launch = json.loads(args.launch) if args.launch else None
     tuned_ms = None
     if launch is None and not args.no_autotune:
-        tune = np.arange(n) if n <= 1024 else np.arange(1024) * n // 1024
+        tune = np.arange(n) if n <= 4096 else np.arange(4096) * n // 4096
         launch, tuned_ms = hv.hv_autotune(reqs[tune], out[:len(tune)])
         stage(f"autotuned: {launch}")
 

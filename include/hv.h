@@ -117,10 +117,12 @@ const char *hv_last_error(void);
 /* Set the calling thread's stream (a hipStream_t; NULL = null stream). */
 int hv_set_stream(void *hip_stream);
 
-/* Launch shape of the query kernel.  hv_render_tiles uses region = 32 with
- * one wavefront per workgroup; through hv_render_tiles_ex, zero fields take
- * block 16, cand_cap 64, waves_per_wg 2 (1 in region mode) and a grid that
- * fills the GPU, and region = 0 selects one wavefront per pixel block. */
+/* Launch shape of the query kernel.  The default (a NULL launch) is
+ * region = 32, one wavefront per workgroup, objs_per_lane 2 and cand_cap
+ * 128.  In a given shape, zero fields take block 16, waves_per_wg 2 (1 in
+ * region mode), objs_per_lane 1, cand_cap 64 * waves_per_wg * objs_per_lane
+ * in region mode (64 otherwise) and a grid that fills the GPU; region = 0
+ * selects one wavefront per pixel block. */
 typedef struct {
     int32_t block;          /* pixel block per wavefront: 8, 16 or 32 (1, 4 or 16 px/lane) */
     int32_t cand_cap;       /* LDS candidate capacity per wavefront, >= 64 */

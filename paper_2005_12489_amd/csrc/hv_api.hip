@@ -78,21 +78,22 @@ int validate_style(const hv_style *style) {
 }
 
 int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s) {
-    // default: one single-wave workgroup per 32x32 region (fastest on the
-    // benchmark workload); hv_launch selects any other shape
+    // default: one single-wave workgroup per 32x32 region, two objects per
+    // lane at a leaf step and a 128-object queue (small LDS, so occupancy is
+    // bound by registers); hv_launch selects any other shape
     s->block = 16;
-    s->cand_cap = 64;
+    s->cand_cap = 128;
     s->waves = 1;
     s->grid = 0;
     s->region = 32;
-    s->opl = 1;
+    s->opl = 2;
     if (l) {
         s->block = l->block ? l->block : 16;
-        s->cand_cap = l->cand_cap ? l->cand_cap : 64;
         s->waves = l->waves_per_wg ? l->waves_per_wg : (l->region ? 1 : 2);
         s->grid = l->grid_wgs;
         s->region = l->region;
         s->opl = l->objs_per_lane ? l->objs_per_lane : 1;
+        s->cand_cap = l->cand_cap ? l->cand_cap : (l->region ? 64 * s->waves * s->opl : 64);
     }
     if (s->opl != 1 && s->opl != 2 && s->opl != 4) return fail(HV_EINVAL, "launch.objs_per_lane must be 1, 2 or 4");
     if (s->region != 0 && s->region != 32 && s->region != 64)
@@ -666,11 +667,13 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     if ((rc = validate_out(scratch_masks))) return rc;
     // candidate shapes: region mode (side, waves, objects per lane, queue)
     // and one wave per block (side, waves, stage capacity); the default first
+    // (region queues at their minimum, 64 x waves x objects per lane: larger
+    // queues cost occupancy)
     static const hv_launch cands[] = {
-        {0, 64, 1, 0, 32, 1},  {0, 128, 1, 0, 32, 2}, {0, 128, 2, 0, 32, 1}, {0, 256, 2, 0, 32, 2},
-        {0, 256, 4, 0, 32, 1}, {0, 128, 2, 0, 64, 1}, {0, 256, 2, 0, 64, 2}, {0, 256, 4, 0, 64, 1},
-        {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},  {16, 128, 4, 0, 0, 1},
-        {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},  {32, 64, 2, 0, 0, 1},
+        {0, 128, 1, 0, 32, 2}, {0, 64, 1, 0, 32, 1},  {0, 256, 1, 0, 32, 4}, {0, 256, 2, 0, 32, 2},
+        {0, 128, 2, 0, 32, 1}, {0, 256, 4, 0, 32, 1}, {0, 128, 1, 0, 64, 2}, {0, 256, 2, 0, 64, 2},
+        {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},
+        {16, 128, 4, 0, 0, 1}, {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
