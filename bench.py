@@ -102,8 +102,10 @@ def make_workload(key: str, scale: float = 1.0):
 
 def query_kernel_name(launch) -> str:
     """Name of the query kernel a launch shape runs (as profilers show it)."""
-    L = launch or {}
-    region = L.get("region", 32) if launch else 32
+    if not launch:
+        return "k_query_region<32, 2>"      # the default shape, whatever its waves per workgroup
+    L = launch
+    region = L.get("region", 0)
     if region:
         return f"k_query_region<{region}, {L.get('objs_per_lane', 1) or 1}>"
     return f"k_query<{L.get('block', 16) or 16}>"

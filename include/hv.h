@@ -117,9 +117,12 @@ const char *hv_last_error(void);
 /* Set the calling thread's stream (a hipStream_t; NULL = null stream). */
 int hv_set_stream(void *hip_stream);
 
-/* Launch shape of the query kernel.  The default (a NULL launch) is
- * region = 32, one wavefront per workgroup, objs_per_lane 2 and cand_cap
- * 128.  In a given shape, zero fields take block 16, waves_per_wg 2 (1 in
+/* Launch shape of the query kernel.  The default (a NULL launch) follows
+ * the batch size n: region = 32, objs_per_lane 2, waves_per_wg 4 for
+ * n < 1024, 2 for n < 4096 and 1 beyond (in a small batch the heaviest
+ * regions set the time and more waves shorten them; a large one fills the
+ * GPU with single-wave groups), and cand_cap 128 * waves_per_wg.  For
+ * anti-aliased output n counts the 4 children of each request.  In a given shape, zero fields take block 16, waves_per_wg 2 (1 in
  * region mode), objs_per_lane 1, cand_cap 64 * waves_per_wg * objs_per_lane
  * in region mode (64 otherwise) and a grid that fills the GPU; region = 0
  * selects one wavefront per pixel block. */
@@ -198,8 +201,10 @@ int hv_render_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
  * it captures one HIP graph [copy staged requests -> frontier kernel ->
  * query kernel] at creation, so a run is one graph launch.  Runs use the
  * two slots in turn; a run waits (on the host) until the run that last used
- * its slot has finished.  launch: the query shape baked into the graphs
- * (NULL = default).  Returns NULL on error (hv_last_error). */
+ * its slot has finished.  launch: the query shape baked into the graphs;
+ * NULL = the default, which then captures one graph per size class of the
+ * default shape that max_requests reaches, and a run launches the one for
+ * its batch size.  Returns NULL on error (hv_last_error). */
 typedef struct hv_batcher hv_batcher;
 hv_batcher *hv_batcher_create(int64_t max_requests, int32_t max_indexes, int32_t max_levels,
                               const hv_launch *launch);
@@ -222,11 +227,11 @@ void hv_batcher_free(hv_batcher *b);
 /* Time a set of launch shapes on a sample batch and return the fastest in
  * *best (and its time per launch in *best_ms, may be NULL).  Each shape
  * runs first on 16, then 128 evenly spread requests of the sample, then on
- * all of it, and is dropped once a part takes more than twice the best
- * time seen on that part.  The result is
- * also cached under the sample's class -- dominant kind, zoom band (z / 4)
- * and radius band (r <= 1, <= 2, <= 4, > 4) -- which hv_render_batch with
- * launch == NULL then uses for batches of that class.  scratch_masks:
+ * all of it, and is dropped once a part takes more than four times the
+ * best time seen on that part.  The result is also cached under the
+ * sample's class -- dominant kind, zoom band (z / 4), radius band (r <= 1,
+ * <= 2, <= 4, > 4) and size band (n < 1024, < 4096, larger) -- which
+ * hv_render_batch with launch == NULL then uses for batches of that class.  scratch_masks:
  * device, n * 8192 bytes.  Synchronous. */
 int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_launch *best, double *best_ms);
 

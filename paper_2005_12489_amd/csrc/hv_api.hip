@@ -77,13 +77,19 @@ int validate_style(const hv_style *style) {
     return HV_OK;
 }
 
-int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s) {
-    // default: one single-wave workgroup per 32x32 region, two objects per
-    // lane at a leaf step and a 128-object queue (small LDS, so occupancy is
-    // bound by registers); hv_launch selects any other shape
+// Wavefronts per workgroup of the default shape for a batch of n requests:
+// in small batches the few heaviest regions set the time, and more waves on
+// each region shorten them; in large ones the GPU is full anyway and one wave
+// per region (occupancy bound by registers) does the least work per pixel.
+int default_waves(int64_t n) { return n < 1024 ? 4 : n < 4096 ? 2 : 1; }
+
+int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s, int64_t n) {
+    // default: one workgroup per 32x32 region with default_waves(n) waves,
+    // two objects per lane at a leaf step and the smallest queue that allows
+    // (small LDS); hv_launch selects any other shape
     s->block = 16;
-    s->cand_cap = 128;
-    s->waves = 1;
+    s->waves = default_waves(n);
+    s->cand_cap = 64 * s->waves * 2;
     s->grid = 0;
     s->region = 32;
     s->opl = 2;
@@ -242,8 +248,10 @@ int plan_batch(const hv_request *reqs, int64_t n, BatchPlan *p) {
 
 // ---------------------------------------------------------------- tuning cache
 struct TuneKey {
-    int kind, zband, rband;
-    bool operator==(const TuneKey &o) const { return kind == o.kind && zband == o.zband && rband == o.rband; }
+    int kind, zband, rband, nband;
+    bool operator==(const TuneKey &o) const {
+        return kind == o.kind && zband == o.zband && rband == o.rband && nband == o.nband;
+    }
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<TuneKey, hv_launch>> g_tune;
@@ -260,7 +268,8 @@ TuneKey batch_key(const hv_request *reqs, int64_t n) {
     std::nth_element(zs.begin(), zs.begin() + n / 2, zs.end());
     std::nth_element(rs.begin(), rs.begin() + n / 2, rs.end());
     const double rm = rs[(size_t)(n / 2)];
-    return TuneKey{seg * 2 >= n ? 1 : 0, zs[(size_t)(n / 2)] / 4, rm <= 1.0 ? 0 : rm <= 2.0 ? 1 : rm <= 4.0 ? 2 : 3};
+    return TuneKey{seg * 2 >= n ? 1 : 0, zs[(size_t)(n / 2)] / 4, rm <= 1.0 ? 0 : rm <= 2.0 ? 1 : rm <= 4.0 ? 2 : 3,
+                   default_waves(n)};
 }
 
 bool tuned_for(const hv_request *reqs, int64_t n, hv_launch *out) {
@@ -433,7 +442,7 @@ int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
     int rc = validate_tiles(tiles, n_tiles);
     if (rc) return rc;
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, index->a.levels, &shape))) return rc;
+    if ((rc = resolve_shape(launch, index->a.levels, &shape, n_tiles))) return rc;
     if (shape.region == 0) return fail(HV_EINVAL, "filling runs in region mode: launch.region must be 32 or 64");
     shape.fill = 1;
     if (hv::query_lds_bytes(shape, index->a.levels) > 65536)
@@ -467,7 +476,7 @@ int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_ti
     if (n_tiles > 0 && (!tiles || !out_masks)) return fail(HV_EINVAL, "tiles or out_masks is NULL");
     if ((rc = validate_tiles(tiles, n_tiles))) return rc;
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, index->a.levels, &shape))) return rc;
+    if ((rc = resolve_shape(launch, index->a.levels, &shape, n_tiles))) return rc;
     if (n_tiles == 0) {
         t_err.clear();
         return HV_OK;
@@ -545,7 +554,7 @@ int hv_render_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     hv_launch tuned;
     if (!launch && tuned_for(reqs, n, &tuned)) launch = &tuned;
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, p.max_levels, &shape))) return rc;
+    if ((rc = resolve_shape(launch, p.max_levels, &shape, n))) return rc;
     if (n == 0) {
         t_err.clear();
         return HV_OK;
@@ -567,7 +576,7 @@ int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, c
             return fail(HV_EINVAL, "request " + std::to_string(k) + ": anti-aliased output needs z <= " +
                                        std::to_string(HV_MAX_ZOOM - 1));
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, p.max_levels, &shape))) return rc;
+    if ((rc = resolve_shape(launch, p.max_levels, &shape, 4 * n))) return rc;
     if (n == 0) {
         t_err.clear();
         return HV_OK;
@@ -611,7 +620,7 @@ int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     hv_launch tuned;
     if (!launch && tuned_for(reqs, n, &tuned)) launch = &tuned;
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, p.max_levels, &shape))) return rc;
+    if ((rc = resolve_shape(launch, p.max_levels, &shape, n))) return rc;
     if ((rc = validate_out(out_masks))) return rc;
     hipEvent_t m[3] = {nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
@@ -651,9 +660,12 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     if (n <= 0) return fail(HV_EINVAL, "the sample is empty");
     // Candidates are timed on growing, evenly spread parts of the sample (16
     // requests, 128, then all of it) and dropped as soon as one part takes
-    // more than twice the best time seen on it, so that a shape that is very
-    // slow on this kind of batch costs one short run, not a full one.
+    // more than four times the best time seen on it, so that a shape that is
+    // very slow on this kind of batch costs one short run, not a full one.
+    // (Not tighter: the best shape for a small part -- more waves per region
+    // -- can be twice as fast there as the best one for the whole sample.)
     constexpr int kStages = 3;
+    constexpr double kDrop = 4.0;
     const int64_t sizes[kStages] = {std::min<int64_t>(n, 16), std::min<int64_t>(n, 128), n};
     BatchPlan plans[kStages];
     for (int st = 0; st < kStages; ++st) {
@@ -666,11 +678,12 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     int rc = HV_OK;
     if ((rc = validate_out(scratch_masks))) return rc;
     // candidate shapes: region mode (side, waves, objects per lane, queue)
-    // and one wave per block (side, waves, stage capacity); the default first
-    // (region queues at their minimum, 64 x waves x objects per lane: larger
-    // queues cost occupancy)
+    // and one wave per block (side, waves, stage capacity); the default's
+    // three shapes first (region queues at their minimum, 64 x waves x
+    // objects per lane: larger queues cost occupancy)
     static const hv_launch cands[] = {
-        {0, 128, 1, 0, 32, 2}, {0, 64, 1, 0, 32, 1},  {0, 256, 1, 0, 32, 4}, {0, 256, 2, 0, 32, 2},
+        {0, 128, 1, 0, 32, 2}, {0, 256, 2, 0, 32, 2}, {0, 512, 4, 0, 32, 2}, {0, 64, 1, 0, 32, 1},
+        {0, 256, 1, 0, 32, 4},
         {0, 128, 2, 0, 32, 1}, {0, 256, 4, 0, 32, 1}, {0, 128, 1, 0, 64, 2}, {0, 256, 2, 0, 64, 2},
         {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},
         {16, 128, 4, 0, 0, 1}, {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},
@@ -683,7 +696,7 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     int best_k = -1;
     for (int k = 0; k < (int)(sizeof(cands) / sizeof(cands[0])) && rc == HV_OK && e == hipSuccess; ++k) {
         hv::LaunchShape shape;
-        if (resolve_shape(&cands[k], p.max_levels, &shape)) continue;  // does not fit this batch
+        if (resolve_shape(&cands[k], p.max_levels, &shape, n)) continue;  // does not fit this batch
         for (int st = 0; st < kStages; ++st) {
             if (st < kStages - 1 && sizes[st] == sizes[st + 1]) continue;
             const BatchPlan &q = plans[st];
@@ -699,13 +712,13 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
                 float ms = 0;
                 if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
                 if (rep > 0 && ms < ms_min) ms_min = ms;  // the first run warms up
-                if (rep == 0 && ms > 2.0 * stage_best[st]) {
+                if (rep == 0 && ms > kDrop * stage_best[st]) {
                     ms_min = ms;  // far behind already: no need to repeat
                     break;
                 }
             }
             if (rc || e != hipSuccess) break;
-            if (ms_min > 2.0 * stage_best[st]) break;
+            if (ms_min > kDrop * stage_best[st]) break;
             if (ms_min < stage_best[st]) {
                 stage_best[st] = ms_min;
                 if (st == kStages - 1) best_k = k;
@@ -739,15 +752,19 @@ struct hv_batcher {
     struct Slot {
         unsigned char *host = nullptr;  // pinned staging
         unsigned char *dev = nullptr;   // device workspace
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph[3] = {nullptr, nullptr, nullptr};  // one per shape class
+        hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
         hipEvent_t done = nullptr;
         bool pending = false;
         int64_t n = 0;
     };
     int64_t max_req = 0;
     int max_ix = 0, max_levels = 0, device = 0;
-    hv::LaunchShape shape{};
+    // shape class k runs batches of up to limit[k] requests (a given launch:
+    // one class; NULL: the default's classes by batch size)
+    int n_shapes = 0;
+    int64_t limit[3] = {0, 0, 0};
+    hv::LaunchShape shape[3]{};
     hv::Workspace w{};
     hipStream_t capture = nullptr;
     Slot slot[2];
@@ -760,8 +777,10 @@ namespace {
 void batcher_release(hv_batcher *b) {
     for (auto &s : b->slot) {
         if (s.pending) (void)hipEventSynchronize(s.done);
-        if (s.exec) (void)hipGraphExecDestroy(s.exec);
-        if (s.graph) (void)hipGraphDestroy(s.graph);
+        for (int k = 0; k < 3; ++k) {
+            if (s.exec[k]) (void)hipGraphExecDestroy(s.exec[k]);
+            if (s.graph[k]) (void)hipGraphDestroy(s.graph[k]);
+        }
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.dev) (void)hipFree(s.dev);
         if (s.host) (void)hipHostFree(s.host);
@@ -788,8 +807,23 @@ hv_batcher *hv_batcher_create(int64_t max_requests, int32_t max_indexes, int32_t
         fail(HV_EINVAL, "max_levels must be in [1, 16]");
         return nullptr;
     }
-    hv::LaunchShape shape;
-    if (resolve_shape(launch, max_levels, &shape)) return nullptr;
+    hv::LaunchShape shape[3];
+    int64_t limit[3] = {max_requests, max_requests, max_requests};
+    int n_shapes = 0;
+    if (launch) {
+        if (resolve_shape(launch, max_levels, &shape[0], max_requests)) return nullptr;
+        n_shapes = 1;
+    } else {
+        // the default's shape classes this batcher can meet: below 1024
+        // requests, below 4096, and beyond
+        static const int64_t bounds[3] = {1023, 4095, int64_t(1) << 24};
+        for (int k = 0; k < 3; ++k) {
+            const int64_t hi = std::min(bounds[k], max_requests);
+            if (resolve_shape(nullptr, max_levels, &shape[n_shapes], hi)) return nullptr;
+            limit[n_shapes++] = hi;
+            if (hi == max_requests) break;
+        }
+    }
     hv_batcher *b = new (std::nothrow) hv_batcher;
     if (!b) {
         fail(HV_ENOMEM, "host allocation failed");
@@ -798,14 +832,19 @@ hv_batcher *hv_batcher_create(int64_t max_requests, int32_t max_indexes, int32_t
     b->max_req = max_requests;
     b->max_ix = max_indexes;
     b->max_levels = max_levels;
-    b->shape = shape;
+    b->n_shapes = n_shapes;
+    for (int k = 0; k < n_shapes; ++k) {
+        b->shape[k] = shape[k];
+        b->limit[k] = limit[k];
+    }
     b->w = hv::workspace_layout(max_requests, max_indexes);
     hipError_t e = hipGetDevice(&b->device);
     int khz = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device);
     b->khz = khz;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-    (void)hv::persistent_grid(shape, max_levels);  // occupancy query outside the capture
+    for (int k = 0; k < n_shapes; ++k)
+        (void)hv::persistent_grid(shape[k], max_levels);  // occupancy queries outside the captures
     for (auto &s : b->slot) {
         if (e == hipSuccess) e = hipHostMalloc((void **)&s.host, b->w.staged_bytes(), hipHostMallocDefault);
         if (e == hipSuccess) {
@@ -813,14 +852,16 @@ hv_batcher *hv_batcher_create(int64_t max_requests, int32_t max_indexes, int32_t
             e = hipMalloc((void **)&s.dev, b->w.total);
         }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t ec = hipMemcpyAsync(s.dev, s.host, b->w.staged_bytes(), hipMemcpyHostToDevice, b->capture);
-            if (ec == hipSuccess) ec = hv::launch_query(b->w, s.dev, max_levels, shape, b->capture);
-            e = hipStreamEndCapture(b->capture, &s.graph);
-            if (ec != hipSuccess) e = ec;
+        for (int k = 0; k < n_shapes && e == hipSuccess; ++k) {
+            e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t ec = hipMemcpyAsync(s.dev, s.host, b->w.staged_bytes(), hipMemcpyHostToDevice, b->capture);
+                if (ec == hipSuccess) ec = hv::launch_query(b->w, s.dev, max_levels, shape[k], b->capture);
+                e = hipStreamEndCapture(b->capture, &s.graph[k]);
+                if (ec != hipSuccess) e = ec;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&s.exec[k], s.graph[k], nullptr, nullptr, 0);
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0);
     }
     if (e != hipSuccess) {
         hip_status(e, "hv_batcher_create");
@@ -850,7 +891,9 @@ int hv_batcher_run(hv_batcher *b, const hv_request *reqs, int64_t n, uint8_t *ou
         s.pending = false;
     }
     hv::stage_host(b->w, p.table.data(), (int)p.table.size(), p.reqs.data(), n, out_masks, s.host);
-    hipError_t e = hipGraphLaunch(s.exec, t_stream);
+    int k = 0;
+    while (k + 1 < b->n_shapes && n > b->limit[k]) ++k;
+    hipError_t e = hipGraphLaunch(s.exec[k], t_stream);
     if (e == hipSuccess) e = hipEventRecord(s.done, t_stream);
     if (e != hipSuccess) return hip_status(e, "hv_batcher_run");
     s.pending = true;

@@ -123,6 +123,29 @@ def test_batcher_graph_replays(hv, torch, world):
         hv.hv_batcher_free(b)
 
 
+def test_batcher_switches_default_shape_by_size(hv, torch, world):
+    """A default batcher holds one graph per size class of the default shape
+    (4 waves per region below 1024 requests, 2 below 4096, 1 beyond); runs
+    that cross the classes in turn equal one fixed explicit shape."""
+    w = world
+    b = hv.hv_batcher_create(4500, max_indexes=3, max_levels=12)
+    rng = np.random.default_rng(12)
+    fixed = dict(region=32, waves_per_wg=1, objs_per_lane=2, cand_cap=128)
+    try:
+        for n in (4500, 300, 2000, 1023, 1024, 4096, 4095, 1):
+            sel = rng.integers(0, len(w["ds"]), n)
+            reqs = hv.requests(np.array(w["hs"], dtype=np.uint64)[w["ds"][sel]], w["tiles"][sel], w["r"][sel])
+            out = torch.empty((n, 8192), dtype=torch.uint8, device="cuda")
+            out.fill_(0x69)
+            log(f"default batcher n={n}")
+            hv.hv_batcher_run(b, reqs, out)
+            torch.cuda.synchronize()
+            ref, _ = _batch(hv, torch, w, sel, launch=fixed)
+            assert np.array_equal(unpack_masks(out.cpu().numpy()), ref), n
+    finally:
+        hv.hv_batcher_free(b)
+
+
 def test_autotune_caches_a_valid_shape(hv, torch, world):
     w = world
     _, reqs = _batch(hv, torch, w)
