@@ -331,7 +331,10 @@ def serve(arrivals: np.ndarray, scheduler: Scheduler, executor, clock=time.perf_
             batches += 1
             sizes.append(len(batch))
             lane = executor.idle_lane()
-        if finished < n and nxt < n and not scheduler.queue and executor.idle_lane() is not None:
+        # Sleep until the next arrival only when nothing is queued or in
+        # flight; while a batch runs the loop keeps polling, so that its
+        # completion is seen at once rather than at the next arrival.
+        if finished < n and nxt < n and not scheduler.queue and scheduler.inflight == 0:
             gap = arrivals[nxt] - (clock() - t0)
             if gap > 2e-4:
                 sleep(gap - 1e-4)
