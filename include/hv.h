@@ -130,7 +130,8 @@ typedef struct {
     int32_t block;          /* pixel block per wavefront: 8, 16 or 32 (1, 4 or 16 px/lane) */
     int32_t cand_cap;       /* LDS candidate capacity per wavefront, >= 64 */
     int32_t waves_per_wg;   /* wavefronts per workgroup: 1, 2 or 4 */
-    int32_t grid_wgs;       /* workgroups of the persistent query kernel; 0 = as many as fit on the GPU */
+    int32_t grid_wgs;       /* workgroups of the persistent query kernel; 0 = ten times as many as fit on
+                               the GPU (filling: one per region, at most 262,144) */
     int32_t region;         /* 0: one wavefront per pixel block; 32 or 64: one workgroup per region of
                                that side whose queued objects are dealt out over all lanes (block is
                                then unused and cand_cap sizes the queue) */
@@ -277,7 +278,12 @@ hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *
  * edge counts when exactly one endpoint lies below the centre's row line, so
  * vertices on the line count once and edges parallel to x never).  tiles,
  * out_masks as for hv_render_tiles (8192 bytes per tile, same bit layout).
- * launch: region mode only (region 32 or 64; NULL = the default shape).
+ * launch: region mode only (region 32 or 64; NULL = region 32 with two
+ * waves per workgroup, objs_per_lane 2, cand_cap 256, at any batch size).
+ * Each region's candidate polygons are those whose bounding box holds one
+ * of its pixel centres; their edges are tested in groups of up to 32
+ * polygons, and only the edges of 8-edge runs whose stored bounding box can
+ * cross one of the region's pixel-centre rows are read.
  * Errors as hv_render_tiles_ex, plus HV_EINVAL for an index that is not a
  * polygon index or a launch with region 0.  The distance-mask entry points
  * reject polygon indexes. */

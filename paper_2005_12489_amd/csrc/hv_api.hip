@@ -53,6 +53,7 @@ hv::DevIndex dev_view(const hv_index *ix) {
     d.order = ix->a.order;
     d.pedges = ix->p.edges;
     d.pfirst = ix->p.first;
+    d.pchunk = ix->p.chunks;
     d.npoly = ix->p.npoly;
     return d;
 }
@@ -443,6 +444,11 @@ int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
     if (rc) return rc;
     hv::LaunchShape shape;
     if ((rc = resolve_shape(launch, index->a.levels, &shape, n_tiles))) return rc;
+    if (!launch) {
+        // filling's default at every batch size: two waves per 32 x 32 region
+        shape.waves = 2;
+        shape.cand_cap = 256;
+    }
     if (shape.region == 0) return fail(HV_EINVAL, "filling runs in region mode: launch.region must be 32 or 64");
     shape.fill = 1;
     if (hv::query_lds_bytes(shape, index->a.levels) > 65536)

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "hv_internal.h"
 
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void k_project_key(const double *__restrict__ 
 #pragma unroll
     for (int c = 0; c < W; ++c) proj[i * W + c] = p[c];
     double cx = p[0], cy = p[1];
-    if (W == 4) {
+    if constexpr (W == 4) {
         cx = 0.5 * (fmin(p[0], p[2]) + fmax(p[0], p[2]));
         cy = 0.5 * (fmin(p[1], p[3]) + fmax(p[1], p[3]));
     }
@@ -128,6 +129,50 @@ __global__ __launch_bounds__(256) void k_polygon_boxes(const double *__restrict_
         y0 = fmin(y0, fmin(g.y, g.w)); y1 = fmax(y1, fmax(g.y, g.w));
     }
     reinterpret_cast<double4 *>(diag)[p] = make_double4(x0, y0, x1, y1);
+}
+
+// Conservative float box of each run of kEdgeChunk consecutive edges of the
+// edge array (runs may straddle polygons): min rounded down, max rounded up,
+// so that every edge of the run lies inside it exactly.
+__device__ inline float float_down(double d) {
+    float f = (float)d;
+    if ((double)f > d) f = nextafterf(f, -INFINITY);
+    return f;
+}
+__device__ inline float float_up(double d) {
+    float f = (float)d;
+    if ((double)f < d) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+__global__ __launch_bounds__(256) void k_edge_chunks(const double *__restrict__ edges, int64_t n,
+                                                     float4 *__restrict__ chunks) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (n + kEdgeChunk - 1) / kEdgeChunk) return;
+    double x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+    const int64_t e1 = min(n, (c + 1) * kEdgeChunk);
+    for (int64_t e = c * kEdgeChunk; e < e1; ++e) {
+        const double4 g = reinterpret_cast<const double4 *>(edges)[e];
+        x0 = fmin(x0, fmin(g.x, g.z)); x1 = fmax(x1, fmax(g.x, g.z));
+        y0 = fmin(y0, fmin(g.y, g.w)); y1 = fmax(y1, fmax(g.y, g.w));
+    }
+    chunks[c] = make_float4(float_down(x0), float_down(y0), float_up(x1), float_up(y1));
+}
+
+// Copies each polygon's edges from input order to the tree's order: wave w
+// of the grid moves sorted polygon w, whose edges start at src_first[order[w]]
+// in `src` and at dst_first[w] in `dst`.
+__global__ __launch_bounds__(256) void k_permute_polygons(const double4 *__restrict__ src,
+                                                          const int64_t *__restrict__ src_first,
+                                                          const uint32_t *__restrict__ order,
+                                                          const int64_t *__restrict__ dst_first, int64_t npoly,
+                                                          double4 *__restrict__ dst) {
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (k >= npoly) return;
+    const int64_t p = order[k];
+    const int64_t s0 = src_first[p], cnt = src_first[p + 1] - s0, d0 = dst_first[k];
+    for (int64_t e = lane; e < cnt; e += 64) dst[d0 + e] = src[s0 + e];
 }
 
 // ------------------------------------------------------------ scans
@@ -363,8 +408,10 @@ BuildResult hip_fail(hipError_t e) {
 void free_poly_arrays(PolyArrays *p) {
     if (p->edges) (void)hipFree(p->edges);
     if (p->first) (void)hipFree(p->first);
+    if (p->chunks) (void)hipFree(p->chunks);
     p->edges = nullptr;
     p->first = nullptr;
+    p->chunks = nullptr;
 }
 
 BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first, int64_t npoly, int flags,
@@ -376,42 +423,84 @@ BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first,
     tree->seg = 1;
     tree->levels = 0;
     if (npoly == 0) return {HV_OK, ""};
-    double *diag = nullptr;
+    // projected edges and offsets in input order first; once the tree has
+    // sorted the polygons, both are rewritten in the tree's order so that the
+    // polygons of one region lie close together in memory
+    double *proj = nullptr, *diag = nullptr;
+    int64_t *in_first = nullptr;
     int *err = nullptr;
-    auto bail = [&](hipError_t e) {
+    auto release = [&]() {
+        if (proj) (void)hipFree(proj);
+        if (in_first) (void)hipFree(in_first);
         if (diag) (void)hipFree(diag);
         if (err) (void)hipFree(err);
+        proj = diag = nullptr;
+        in_first = nullptr;
+        err = nullptr;
+    };
+    auto bail = [&](hipError_t e) {
+        release();
         free_poly_arrays(poly);
+        free_index_arrays(tree);
         return hip_fail(e);
     };
     hipError_t e;
-    if ((e = hipMalloc((void **)&poly->edges, sizeof(double) * 4 * (size_t)n)) != hipSuccess) return bail(e);
-    if ((e = hipMalloc((void **)&poly->first, sizeof(int64_t) * (size_t)(npoly + 1))) != hipSuccess) return bail(e);
+    if ((e = hipMalloc((void **)&proj, sizeof(double) * 4 * (size_t)n)) != hipSuccess) return bail(e);
+    if ((e = hipMalloc((void **)&in_first, sizeof(int64_t) * (size_t)(npoly + 1))) != hipSuccess) return bail(e);
     if ((e = hipMalloc((void **)&diag, sizeof(double) * 4 * (size_t)npoly)) != hipSuccess) return bail(e);
     if ((e = hipMalloc((void **)&err, sizeof(int))) != hipSuccess) return bail(e);
-    if ((e = hipMemcpyAsync(poly->first, first, sizeof(int64_t) * (size_t)(npoly + 1), hipMemcpyHostToDevice, st)) !=
+    if ((e = hipMemcpyAsync(in_first, first, sizeof(int64_t) * (size_t)(npoly + 1), hipMemcpyHostToDevice, st)) !=
         hipSuccess)
         return bail(e);
     if ((e = hipMemsetAsync(err, 0, sizeof(int), st)) != hipSuccess) return bail(e);
-    hipLaunchKernelGGL(k_project_edges, dim3((uint32_t)cdiv(n, 256)), dim3(256), 0, st, edges, n, merc, poly->edges,
-                       err);
-    hipLaunchKernelGGL(k_polygon_boxes, dim3((uint32_t)cdiv(npoly, 256)), dim3(256), 0, st, poly->edges, poly->first,
-                       npoly, diag);
+    hipLaunchKernelGGL(k_project_edges, dim3((uint32_t)cdiv(n, 256)), dim3(256), 0, st, edges, n, merc, proj, err);
+    hipLaunchKernelGGL(k_polygon_boxes, dim3((uint32_t)cdiv(npoly, 256)), dim3(256), 0, st, proj, in_first, npoly,
+                       diag);
     if ((e = hipGetLastError()) != hipSuccess) return bail(e);
     int herr = 0;
     if ((e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return bail(e);
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e);
     if (herr) {
-        (void)hipFree(diag);
-        (void)hipFree(err);
+        release();
         free_poly_arrays(poly);
         return {HV_EINVAL, "edges hold a non-finite coordinate, |lon| > 180 or |lat| > 90"};
     }
     const BuildResult r = build_index(diag, HV_SEGMENTS | HV_INPUT_MERC01, npoly, st, tree);
-    (void)hipFree(diag);
-    (void)hipFree(err);
-    if (r.status != HV_OK) free_poly_arrays(poly);
-    else tree->device_bytes += (int64_t)(sizeof(double) * 4 * (size_t)n + sizeof(int64_t) * (size_t)(npoly + 1));
+    if (r.status != HV_OK) {
+        release();
+        free_poly_arrays(poly);
+        return r;
+    }
+    // offsets in the tree's order (host prefix sums over the sorted counts)
+    std::vector<uint32_t> order((size_t)npoly);
+    std::vector<int64_t> sorted_first((size_t)npoly + 1);
+    if ((e = hipMemcpy(order.data(), tree->order, sizeof(uint32_t) * (size_t)npoly, hipMemcpyDeviceToHost)) !=
+        hipSuccess)
+        return bail(e);
+    sorted_first[0] = 0;
+    for (int64_t k = 0; k < npoly; ++k) {
+        const uint32_t p = order[(size_t)k];
+        sorted_first[(size_t)k + 1] = sorted_first[(size_t)k] + (first[p + 1] - first[p]);
+    }
+    const int64_t nchunk = cdiv(n, kEdgeChunk);
+    if ((e = hipMalloc((void **)&poly->edges, sizeof(double) * 4 * (size_t)n)) != hipSuccess) return bail(e);
+    if ((e = hipMalloc((void **)&poly->first, sizeof(int64_t) * (size_t)(npoly + 1))) != hipSuccess) return bail(e);
+    if (nchunk > 0 && (e = hipMalloc((void **)&poly->chunks, sizeof(float4) * (size_t)nchunk)) != hipSuccess)
+        return bail(e);
+    if ((e = hipMemcpyAsync(poly->first, sorted_first.data(), sizeof(int64_t) * (size_t)(npoly + 1),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e);
+    hipLaunchKernelGGL(k_permute_polygons, dim3((uint32_t)cdiv(npoly, 4)), dim3(256), 0, st,
+                       reinterpret_cast<const double4 *>(proj), in_first, tree->order, poly->first, npoly,
+                       reinterpret_cast<double4 *>(poly->edges));
+    if (nchunk > 0)
+        hipLaunchKernelGGL(k_edge_chunks, dim3((uint32_t)cdiv(nchunk, 256)), dim3(256), 0, st, poly->edges, n,
+                           poly->chunks);
+    if ((e = hipGetLastError()) != hipSuccess) return bail(e);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e);
+    release();
+    tree->device_bytes += (int64_t)(sizeof(double) * 4 * (size_t)n + sizeof(int64_t) * (size_t)(npoly + 1) +
+                                    sizeof(float4) * (size_t)nchunk);
     return r;
 }
 

@@ -11,6 +11,7 @@ namespace hv {
 
 constexpr int kLeaf = 16;        // objects per leaf
 constexpr int kFan = 16;         // children per inner node
+constexpr int kEdgeChunk = 8;    // polygon edges per chunk box (filling)
 constexpr int kMaxLevels = 16;   // node levels (2e9 objects need 8)
 constexpr int kLevelShift = 27;  // stack entry: level << 27 | node index
 constexpr uint32_t kIdxMask = (1u << kLevelShift) - 1;
@@ -27,8 +28,9 @@ struct DevIndex {
     // polygon indexes only (filling): the tree above holds the polygons'
     // bounding boxes as diagonals, in sorted order
     const uint32_t *order;       // sorted position -> polygon
-    const double *pedges;        // edges in polygon order, 4 doubles each
-    const int64_t *pfirst;       // polygon p owns edges [pfirst[p], pfirst[p + 1])
+    const double *pedges;        // edges, 4 doubles each, polygon after polygon in sorted order
+    const int64_t *pfirst;       // the polygon at sorted position k owns edges [pfirst[k], pfirst[k + 1])
+    const float4 *pchunk;        // chunk c: a box holding edges [kEdgeChunk c, kEdgeChunk (c + 1))
     int64_t npoly;
 };
 
@@ -63,15 +65,18 @@ struct IndexArrays {
 // Device arrays of a polygon index beyond its box tree (freed by
 // free_poly_arrays).
 struct PolyArrays {
-    double *edges = nullptr;     // projected, polygon order
-    int64_t *first = nullptr;    // npoly + 1
+    double *edges = nullptr;     // projected, polygon after polygon in the tree's sorted order
+    int64_t *first = nullptr;    // npoly + 1 offsets into edges, by sorted position
+    float4 *chunks = nullptr;    // ceil(n_edges / kEdgeChunk) conservative float boxes
     int64_t npoly = 0, n_edges = 0;
 };
 
 // Builds a polygon index: projects `edges` (device, n x 4 lon0, lat0, lon1,
-// lat1, or normalised with HV_INPUT_MERC01 in flags) in their given order,
-// copies `first` (host, npoly + 1), computes each polygon's bounding box and
-// builds the Hilbert R-tree over those boxes (as diagonal segments).
+// lat1, or normalised with HV_INPUT_MERC01 in flags; polygon p owns edges
+// [first[p], first[p + 1]), `first` on the host), computes each polygon's
+// bounding box, builds the Hilbert R-tree over those boxes (as diagonal
+// segments), then stores the edges polygon after polygon in the tree's
+// order, with a conservative box per kEdgeChunk edges.
 BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first, int64_t npoly, int flags,
                            hipStream_t stream, IndexArrays *tree, PolyArrays *poly);
 void free_poly_arrays(PolyArrays *p);

@@ -933,17 +933,33 @@ __global__ __launch_bounds__(256) void k_query_region(DevBatch B, int cap, int m
 // (even-odd rule, holes included).  The fill is the OR over polygons.
 // Casting the ray towards -x instead of towards the nearer side of the box
 // gives the same parity for closed rings.
+// Queued polygons are tested in groups of up to kFillGroup: the edge chunks
+// of the whole group are dealt out over all lanes, each polygon toggling its
+// own parity rows, and the rows are ORed into the fill after the group.  A
+// chunk's conservative box decides whether any of its edges can cross a row
+// centre line of the region left of its last pixel centre; only then are its
+// edges read.
+constexpr int kFillGroup = 32;
+constexpr int64_t kFillGrid = 262144;  // default workgroups of a filling launch (at most one per region)
+
 struct FillLds {
     uint32_t *stk;
-    uint32_t *cand;  // candidate polygons
-    uint32_t *mask;  // RS rows x RS/32 words: filled so far
-    uint32_t *par;   // parity rows of the polygon being tested
-    int *ctl;        // [0] stack size, [1] candidates
+    uint32_t *cand;   // candidate polygons
+    uint32_t *mask;   // RS rows x RS/32 words: filled so far
+    uint32_t *par;    // kFillGroup x RS rows x RS/32 words: parity rows of the group (zero between groups)
+    int64_t *efirst;  // edge range [efirst, eend) of each polygon of the group
+    int64_t *eend;
+    int64_t *cpre;    // kFillGroup + 1 prefix sums of the group's chunk counts
+    int64_t *lc;      // one per thread: chunks that passed their box test this round
+    uint8_t *lq;      // and the group polygon each belongs to
+    int *ctl;         // [0] stack size, [1] candidates, [2], [3] passed chunks (alternate rounds)
 };
 
 __host__ __device__ inline size_t fill_lds_bytes(int cap, int levels, int threads, int rs) {
-    return align16((size_t)region_stack_words(levels, threads) * 4) + align16((size_t)cap * 4) +
-           2 * align16((size_t)rs * (rs / 32) * 4) + 16;
+    const size_t rows = (size_t)rs * (rs / 32) * 4;
+    return align16((size_t)region_stack_words(levels, threads) * 4) + align16((size_t)cap * 4) + align16(rows) +
+           align16(kFillGroup * rows) + 2 * align16(kFillGroup * 8) + align16((kFillGroup + 1) * 8) +
+           align16((size_t)threads * 8) + align16((size_t)threads) + 16;
 }
 
 template <int RS>
@@ -976,6 +992,8 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
     if (tid == 0) {
         ctl[0] = 0;
         ctl[1] = 0;
+        ctl[2] = 0;
+        ctl[3] = 0;
     }
     __syncthreads();
     for (int base = 0; base < fcount; base += nthr) {
@@ -990,38 +1008,103 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
     }
     __syncthreads();
 
-    // Tests the queued polygons one by one; true once the region is all filled.
+    // Tests the queued polygons, a group at a time; true once the region is
+    // all filled.
     auto test = [&]() -> bool {
         const int nc = ctl[1];
-        for (int c = 0; c < nc; ++c) {
-            const int64_t pid = L.cand[c];
-            for (int k = tid; k < RS * W; k += nthr) par[k] = 0;
+        for (int c0 = 0; c0 < nc; c0 += kFillGroup) {
+            const int nb = min(kFillGroup, nc - c0);
+            if (tid < 64) {  // edge ranges of the group and the prefix sums of their chunk counts
+                int64_t f = 0, fe = 0;
+                long long x = 0;
+                if (lane < nb) {
+                    const int64_t pid = L.cand[c0 + lane];
+                    f = ix.pfirst[pid];
+                    fe = ix.pfirst[pid + 1];
+                    x = fe > f ? (fe - 1) / kEdgeChunk - f / kEdgeChunk + 1 : 0;
+                }
+#pragma unroll
+                for (int o = 1; o < kFillGroup; o <<= 1) {
+                    const long long y = __shfl_up(x, o, 64);
+                    if (lane >= o) x += y;
+                }
+                if (lane < nb) {
+                    L.efirst[lane] = f;
+                    L.eend[lane] = fe;
+                    L.cpre[lane + 1] = x;
+                }
+                if (lane == 0) L.cpre[0] = 0;
+            }
             __syncthreads();
-            const int64_t e1 = ix.pfirst[pid + 1];
-            for (int64_t e = ix.pfirst[pid] + tid; e < e1; e += nthr) {
-                const double4 g = reinterpret_cast<const double4 *>(ix.pedges)[e];
-                const double ax = g.x * S - ox, ay = g.y * S - oy, bx = g.z * S - ox, by = g.w * S - oy;
-                if (ay == by || fmin(ax, bx) >= i0 + (RS - 0.5)) continue;  // no crossing left of a pixel
-                // candidate rows, one wider on each side; each is checked exactly
-                const int jlo = (int)fmax(ceil(fmin(ay, by) - j0 - 0.5) - 1.0, 0.0);
-                const int jhi = (int)fmin(ceil(fmax(ay, by) - j0 - 0.5), RS - 1.0);
-                for (int j = jlo; j <= jhi; ++j) {
-                    const double yc = j0 + (double)j + 0.5;
-                    if ((ay > yc) == (by > yc)) continue;
-                    const double xc = ax + (yc - ay) * (bx - ax) / (by - ay);
-                    const double f = floor(xc - i0 - 0.5) + 1.0;  // first pixel strictly right of xc
-                    if (f >= RS) continue;
-                    const int k0 = f <= 0.0 ? 0 : (int)f;
-                    for (int wd = k0 >> 5; wd < W; ++wd) {
-                        const int lo = k0 - 32 * wd;
-                        atomicXor(&par[j * W + wd], lo <= 0 ? 0xffffffffu : (0xffffffffu << lo));
+            // rounds of nthr chunks: each lane tests one chunk box, then the
+            // edges of the chunks that passed are dealt out one per lane
+            const int64_t tot = L.cpre[nb];
+            int round = 0;
+            for (int64_t base = 0; base < tot; base += nthr, ++round) {
+                int *npass = &ctl[2 + (round & 1)];
+                const int64_t g = base + tid;
+                bool pass = false;
+                int q = 0;
+                int64_t c = 0;
+                if (g < tot) {
+                    // the group's polygon holding chunk g: largest q with cpre[q] <= g
+#pragma unroll
+                    for (int h = kFillGroup / 2; h > 0; h >>= 1)
+                        if (q + h < nb && L.cpre[q + h] <= g) q += h;
+                    c = L.efirst[q] / kEdgeChunk + (g - L.cpre[q]);
+                    // the box bounds every edge's pixel coordinates (S is a
+                    // power of two and rounding is monotonic), so a chunk with
+                    // an edge the edge test below would use always passes
+                    const float4 cb = ix.pchunk[c];
+                    pass = (double)cb.x * S - ox < i0 + (RS - 0.5) &&
+                           fmax(ceil((double)cb.y * S - oy - j0 - 0.5) - 1.0, 0.0) <=
+                               fmin(ceil((double)cb.w * S - oy - j0 - 0.5), RS - 1.0);
+                }
+                const int slot = wave_alloc(npass, __ballot(pass), lane);
+                if (pass) {
+                    L.lc[slot] = c;
+                    L.lq[slot] = (uint8_t)q;
+                }
+                __syncthreads();
+                const int np = *npass;
+                for (int it = tid; it < np * kEdgeChunk; it += nthr) {
+                    const int sl = it / kEdgeChunk;
+                    const int qq = L.lq[sl];
+                    const int64_t e = L.lc[sl] * kEdgeChunk + it % kEdgeChunk;
+                    if (e < L.efirst[qq] || e >= L.eend[qq]) continue;
+                    const double4 gd = reinterpret_cast<const double4 *>(ix.pedges)[e];
+                    const double ax = gd.x * S - ox, ay = gd.y * S - oy, bx = gd.z * S - ox, by = gd.w * S - oy;
+                    if (ay == by || fmin(ax, bx) >= i0 + (RS - 0.5)) continue;  // no crossing left of a pixel
+                    uint32_t *pq = par + qq * (RS * W);
+                    // candidate rows, one wider on each side; each is checked exactly
+                    const int jlo = (int)fmax(ceil(fmin(ay, by) - j0 - 0.5) - 1.0, 0.0);
+                    const int jhi = (int)fmin(ceil(fmax(ay, by) - j0 - 0.5), RS - 1.0);
+                    for (int j = jlo; j <= jhi; ++j) {
+                        const double yc = j0 + (double)j + 0.5;
+                        if ((ay > yc) == (by > yc)) continue;
+                        const double xc = ax + (yc - ay) * (bx - ax) / (by - ay);
+                        const double fx = floor(xc - i0 - 0.5) + 1.0;  // first pixel strictly right of xc
+                        if (fx >= RS) continue;
+                        const int k0 = fx <= 0.0 ? 0 : (int)fx;
+                        for (int wd = k0 >> 5; wd < W; ++wd) {
+                            const int lo = k0 - 32 * wd;
+                            atomicXor(&pq[j * W + wd], lo <= 0 ? 0xffffffffu : (0xffffffffu << lo));
+                        }
                     }
                 }
+                __syncthreads();
+                // this round's counter is free again (the next round uses the
+                // other one, cleared before this round's first barrier)
+                if (tid == 0) *npass = 0;
             }
             __syncthreads();
             bool full = true;
             for (int k = tid; k < RS * W; k += nthr) {
-                const uint32_t v = mask[k] | par[k];
+                uint32_t v = mask[k];
+                for (int q = 0; q < nb; ++q) {
+                    v |= par[q * (RS * W) + k];
+                    par[q * (RS * W) + k] = 0;
+                }
                 mask[k] = v;
                 full &= v == 0xffffffffu;
             }
@@ -1064,7 +1147,7 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                 keep = cx0 <= cx1 && cy0 <= cy1;
             }
             const int slot = wave_alloc(&ctl[1], __ballot(keep), lane);
-            if (keep) L.cand[slot] = ix.order[o];
+            if (keep) L.cand[slot] = (uint32_t)o;  // edges and offsets are stored by sorted position
         }
         __syncthreads();
         if (ctl[1] > cap - nthr && test()) {
@@ -1089,10 +1172,19 @@ __global__ __launch_bounds__(256) void k_fill_region(DevBatch B, int cap, int ma
     FillLds L;
     L.stk = reinterpret_cast<uint32_t *>(base);
     unsigned char *cb = base + align16((size_t)region_stack_words(max_levels, blockDim.x) * 4);
+    constexpr size_t kRows = (size_t)RS * (RS / 32) * 4;
     L.cand = reinterpret_cast<uint32_t *>(cb);
     L.mask = reinterpret_cast<uint32_t *>(cb + align16((size_t)cap * 4));
-    L.par = L.mask + align16((size_t)RS * (RS / 32) * 4) / 4;
-    L.ctl = reinterpret_cast<int *>(L.par + align16((size_t)RS * (RS / 32) * 4) / 4);
+    L.par = L.mask + align16(kRows) / 4;
+    L.efirst = reinterpret_cast<int64_t *>(L.par + align16(kFillGroup * kRows) / 4);
+    L.eend = L.efirst + align16(kFillGroup * 8) / 8;
+    L.cpre = L.eend + align16(kFillGroup * 8) / 8;
+    L.lc = L.cpre + align16((kFillGroup + 1) * 8) / 8;
+    L.lq = reinterpret_cast<uint8_t *>(L.lc + blockDim.x);
+    L.ctl = reinterpret_cast<int *>(L.lq + align16(blockDim.x));
+    // the group parity rows start at zero and every group clears what it used
+    for (int k = threadIdx.x; k < kFillGroup * RS * (RS / 32); k += blockDim.x) L.par[k] = 0;
+    __syncthreads();
     uint8_t *const out = B.hdr->out;
     zero_empty_tiles(B, out);
     const ItemMap im(B.hdr->counter, RPT);
@@ -1155,6 +1247,7 @@ size_t query_lds_bytes(const LaunchShape &s, int max_levels) {
 }
 
 Workspace workspace_layout(int64_t n_req, int n_ix) {
+    static_assert(sizeof(BatchHeader) <= 256, "the header must fit before the index table");
     Workspace w;
     w.n_req = n_req;
     w.hdr_off = 0;
@@ -1249,7 +1342,11 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, 
                                       : ((256 / s.block) * (256 / s.block) + s.waves - 1) / s.waves;
     // (the item count per XCD is rounded up to whole tiles)
     const int64_t need = n_req * per_tile;
-    int64_t grid = s.grid > 0 ? s.grid : persistent_grid(s, max_levels);
+    // filling's regions differ in cost by orders of magnitude (clusters of
+    // small polygons next to empty sea), so by default each gets its own
+    // workgroup and the dispatcher balances them; the distance kernels keep a
+    // persistent grid
+    int64_t grid = s.grid > 0 ? s.grid : s.fill ? kFillGrid : persistent_grid(s, max_levels);
     if (grid > need) grid = need;
     const dim3 g((uint32_t)grid), b((uint32_t)(64 * s.waves));
     if (s.fill && s.region == 64) hipLaunchKernelGGL(k_fill_region<64>, g, b, lds, st, B, s.cand_cap, max_levels);
