@@ -226,7 +226,8 @@ int hv_batcher_latency(hv_batcher *b, double *latency_us, int64_t n);
 void hv_batcher_free(hv_batcher *b);
 
 /* Time a set of launch shapes on a sample batch and return the fastest in
- * *best (and its time per launch in *best_ms, may be NULL).  Each shape
+ * *best (and its time per launch in *best_ms, may be NULL: the frontier and
+ * query kernels between HIP events, the fastest of the repeats).  Each shape
  * runs first on 16, then 128 evenly spread requests of the sample, then on
  * all of it, and is dropped once a part takes more than four times the
  * best time seen on that part.  The result is also cached under the

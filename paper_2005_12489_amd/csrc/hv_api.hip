@@ -694,10 +694,16 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
         {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},
         {16, 128, 4, 0, 0, 1}, {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},
     };
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e != hipSuccess) return hip_status(e, "hv_autotune");
+    // events around the two kernels only: staging and the workspace
+    // allocation are the same for every shape and only add noise
+    hipEvent_t m[3] = {nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&m[k]);
+    if (e != hipSuccess) {
+        for (int k = 0; k < 3; ++k)
+            if (m[k]) (void)hipEventDestroy(m[k]);
+        return hip_status(e, "hv_autotune");
+    }
     double stage_best[kStages] = {1e300, 1e300, 1e300};
     int best_k = -1;
     for (int k = 0; k < (int)(sizeof(cands) / sizeof(cands[0])) && rc == HV_OK && e == hipSuccess; ++k) {
@@ -709,14 +715,12 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
             const int reps = st == kStages - 1 ? 4 : 2;
             float ms_min = 1e30f;
             for (int rep = 0; rep < reps; ++rep) {
-                if ((e = hipEventRecord(e0, t_stream)) != hipSuccess) break;
                 rc = run_batch(q.table.data(), (int)q.table.size(), q.max_levels, q.reqs.data(), sizes[st],
-                               scratch_masks, shape, "hv_autotune");
+                               scratch_masks, shape, "hv_autotune", m);
                 if (rc) break;
-                if ((e = hipEventRecord(e1, t_stream)) != hipSuccess) break;
-                if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+                if ((e = hipEventSynchronize(m[2])) != hipSuccess) break;
                 float ms = 0;
-                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+                if ((e = hipEventElapsedTime(&ms, m[0], m[2])) != hipSuccess) break;
                 if (rep > 0 && ms < ms_min) ms_min = ms;  // the first run warms up
                 if (rep == 0 && ms > kDrop * stage_best[st]) {
                     ms_min = ms;  // far behind already: no need to repeat
@@ -731,8 +735,7 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (int k = 0; k < 3; ++k) (void)hipEventDestroy(m[k]);
     if (rc) return rc;
     if (e != hipSuccess) return hip_status(e, "hv_autotune");
     if (best_k < 0) return fail(HV_EINVAL, "no candidate shape fits this batch");
