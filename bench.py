@@ -441,13 +441,17 @@ def main():
 
     per_tile = None
     if not args.no_per_tile:
+        # one launch per tile in the library's shape for a single request
+        # (the batch's tuned shape is chosen for thousands of them), unless a
+        # shape was given on the command line
+        one = json.loads(args.launch) if args.launch else None
         m = min(n, 4096)
         pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(m)]
         torch.cuda.synchronize()
         q0 = time.perf_counter()
         for k in range(m):
             pe[k][0].record()
-            hv.hv_render_batch(reqs[k:k + 1], out[k], launch)
+            hv.hv_render_batch(reqs[k:k + 1], out[k], one)
             pe[k][1].record()
         torch.cuda.synchronize()
         q1 = time.perf_counter()
