@@ -137,6 +137,9 @@ typedef struct {
                                then unused and cand_cap sizes the queue) */
     int32_t objs_per_lane;  /* region mode: objects each lane loads per leaf step, 1, 2 or 4;
                                cand_cap must be >= 64 * waves_per_wg * objs_per_lane */
+    int32_t cull_nodes;     /* cull depth of the per-tile pass: it descends the tree while the next
+                               level holds at most this many nodes that meet the tile, 1..256
+                               (0 = 256); blocks and regions then walk on from those nodes */
 } hv_launch;
 
 /* hv_render_tiles with an explicit launch shape (autotuning and variant
@@ -144,8 +147,8 @@ typedef struct {
  * cases: block not 8, 16 or 32, cand_cap < 64 or > 4096, waves_per_wg not 1,
  * 2 or 4, grid_wgs outside [0, 2^20], region not 0, 32 or 64,
  * objs_per_lane not 1, 2 or 4, cand_cap below 64 * waves_per_wg *
- * objs_per_lane in region mode, or a shape needing more than 64 KiB of LDS
- * per workgroup. */
+ * objs_per_lane in region mode, cull_nodes outside [0, 256], or a shape
+ * needing more than 64 KiB of LDS per workgroup. */
 int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
                        const hv_style *style, uint8_t *out_masks, const hv_launch *launch);
 

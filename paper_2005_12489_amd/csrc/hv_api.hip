@@ -103,6 +103,8 @@ int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s, int64_
         s->cand_cap = l->cand_cap ? l->cand_cap : (l->region ? 64 * s->waves * s->opl : 64);
     }
     if (s->opl != 1 && s->opl != 2 && s->opl != 4) return fail(HV_EINVAL, "launch.objs_per_lane must be 1, 2 or 4");
+    s->cull = l && l->cull_nodes ? l->cull_nodes : hv::kFrontier;
+    if (s->cull < 1 || s->cull > hv::kFrontier) return fail(HV_EINVAL, "launch.cull_nodes must be in [0, 256]");
     if (s->region != 0 && s->region != 32 && s->region != 64)
         return fail(HV_EINVAL, "launch.region must be 0, 32 or 64");
     if (s->region && s->cand_cap < 64 * s->waves * s->opl)
@@ -687,9 +689,10 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     // and one wave per block (side, waves, stage capacity); the default's
     // three shapes first (region queues at their minimum, 64 x waves x
     // objects per lane: larger queues cost occupancy)
+    // (the last field, cull depth, 0 = 256 frontier nodes)
     static const hv_launch cands[] = {
-        {0, 128, 1, 0, 32, 2}, {0, 256, 2, 0, 32, 2}, {0, 512, 4, 0, 32, 2}, {0, 64, 1, 0, 32, 1},
-        {0, 256, 1, 0, 32, 4},
+        {0, 128, 1, 0, 32, 2, 0}, {0, 256, 2, 0, 32, 2, 0}, {0, 512, 4, 0, 32, 2, 0}, {0, 128, 1, 0, 32, 2, 128},
+        {0, 128, 1, 0, 32, 2, 32}, {0, 512, 4, 0, 32, 2, 32}, {0, 64, 1, 0, 32, 1}, {0, 256, 1, 0, 32, 4},
         {0, 128, 2, 0, 32, 1}, {0, 256, 4, 0, 32, 1}, {0, 128, 1, 0, 64, 2}, {0, 256, 2, 0, 64, 2},
         {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},
         {16, 128, 4, 0, 0, 1}, {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},

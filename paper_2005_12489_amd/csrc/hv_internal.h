@@ -12,6 +12,7 @@ namespace hv {
 constexpr int kLeaf = 16;        // objects per leaf
 constexpr int kFan = 16;         // children per inner node
 constexpr int kEdgeChunk = 8;    // polygon edges per chunk box (filling)
+constexpr int kFrontier = 256;   // most nodes in a tile's frontier
 constexpr int kMaxLevels = 16;   // node levels (2e9 objects need 8)
 constexpr int kLevelShift = 27;  // stack entry: level << 27 | node index
 constexpr uint32_t kIdxMask = (1u << kLevelShift) - 1;
@@ -95,6 +96,7 @@ struct LaunchShape {
     int region;       // 0: one wave per block; 32 or 64: one workgroup per region of that side
     int opl;          // region mode: objects loaded per lane at a leaf step (1, 2 or 4)
     int fill = 0;     // 1: polygon filling (region mode) instead of the distance masks
+    int cull = kFrontier;  // frontier cap of the per-tile pass (cull depth)
 };
 
 // LDS bytes per workgroup for a shape and the deepest index of a batch.

@@ -38,7 +38,6 @@
 namespace hv {
 namespace {
 
-constexpr int kFrontier = 256;              // nodes per tile frontier
 constexpr uint32_t kBigFlag = 0x80000000u;  // staged object tested pixel-parallel
 constexpr int kSmallArea = 48;              // largest pixel range tested object-parallel
 constexpr double kRangeEps = 1e-7;          // px, widens every pixel range
@@ -95,7 +94,9 @@ __device__ inline uint64_t wave_or64(uint64_t v) {
 
 // rs: region side of the query kernel that follows (32 or 64), for which the
 // frontier records the regions its nodes can reach; 0 marks every part.
-__global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs) {
+// cull (1..kFrontier): the cull depth -- the walk goes one level deeper only
+// while that level holds at most cull nodes meeting the tile.
+__global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs, int cull) {
     __shared__ uint32_t buf[4][2][kFrontier];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps per-tile values scalar
@@ -140,12 +141,12 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs) {
             }
             const uint64_t hm = __ballot(hit);
             const int pos = nn + (int)lanes_below(hm);
-            if (hit && pos < kFrontier) nxt[pos] = (uint32_t)child;
+            if (hit && pos < cull) nxt[pos] = (uint32_t)child;
             nn += __popcll(hm);
-            if (nn > kFrontier) break;
+            if (nn > cull) break;
         }
         __builtin_amdgcn_wave_barrier();
-        if (nn > kFrontier) break;
+        if (nn > cull) break;
         uint32_t *tmp = cur;
         cur = nxt;
         nxt = tmp;
@@ -1334,7 +1335,7 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, 
     const DevBatch B = device_batch(w, dws);
     hipError_t e;
     if (marks && (e = hipEventRecord(marks[0], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B, s.region);
+    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B, s.region, s.cull);
     if (marks && (e = hipEventRecord(marks[1], st)) != hipSuccess) return e;
     const size_t lds = query_lds_bytes(s, max_levels);
     // never more workgroups than there are blocks (or regions) to render

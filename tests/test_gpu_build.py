@@ -106,13 +106,17 @@ SHAPES += [dict(region=rs, cand_cap=64 * w * o, waves_per_wg=w, objs_per_lane=o)
            for rs in (32, 64) for w in (1, 2, 4) for o in (1, 2, 4)]
 SHAPES += [dict(region=rs, cand_cap=512, waves_per_wg=w, objs_per_lane=o, grid_wgs=7)
            for rs in (32, 64) for w, o in ((1, 1), (2, 4))]
+# cull depth: from the root alone to a deep frontier
+SHAPES += [dict(region=32, cand_cap=128, waves_per_wg=1, objs_per_lane=2, cull_nodes=c) for c in (1, 3, 16, 64, 255)]
+SHAPES += [dict(block=16, cand_cap=64, waves_per_wg=2, cull_nodes=c) for c in (1, 40)]
 
 
 def test_launch_shapes_identical(hv, torch):
     """Every launch shape (block size, LDS candidate capacity -- 64 forces a
     flush after every leaf step --, waves per workgroup, persistent grid
     size, including a 7-workgroup grid that makes each wave loop over many
-    blocks) gives bit-identical masks."""
+    blocks, and the cull depth of the per-tile pass) gives bit-identical
+    masks."""
     segs = hvgen.gen_c2_segments(seed=8, n_segments=400_000)
     pts = hvgen.gen_c3_points(300_000)
     edges = hvgen.gen_c4_edges(seed=12, min_edges=60_000, batch_polygons=2000)

@@ -115,6 +115,8 @@ def test_fill_random_rings_holes_overlaps(hv, torch):
         check(got, ref, f"fill random rings z={z}")
         assert np.array_equal(fill(hv, torch, h, tiles, dict(region=64, waves_per_wg=4, cand_cap=256)), got)
         assert np.array_equal(fill(hv, torch, h, tiles, dict(region=32, waves_per_wg=2, cand_cap=128)), got)
+        assert np.array_equal(fill(hv, torch, h, tiles, dict(region=32, waves_per_wg=1, cand_cap=128,
+                                                              cull_nodes=2)), got)
         hv.hv_free(h)
 
 
