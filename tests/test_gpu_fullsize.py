@@ -1,6 +1,7 @@
 """The full-size workloads in the launch the benchmark times (the graph-
 captured batcher, default shape): 1e9 clustered points with 10,000 requests
-at zooms 0-18, and 2e8 polygon edges with 4,096 requests at zooms 2-20.
+at zooms 0-18, and 2e8 polygon edges with 4,096 requests at zooms 2-20, as
+distance masks and as polygon fills (hv_render_fill, default shape).
 
 At this size the oracle cannot index everything on the host, so it checks
 sampled tiles at zoom >= 10 over the objects whose bounding box comes within
@@ -153,3 +154,67 @@ def test_c4_full_size(hv, torch):
     pick = _deep_sample(tiles, 6)
     log(f"c4 full size: oracle on {len(pick)} sampled tiles")
     _check_sample(full, edges, oracle.POLYGON_EDGES, tiles, r, pick, "c4-full")
+
+
+def _check_fill_sample(packed, edges, first, tiles, pick, what):
+    """Oracle fill of sampled tiles over the polygons whose bounding box meets
+    the tile grown by 4 px (a superset of every polygon that can hold one of
+    its pixel centres)."""
+    lo_x = np.minimum.reduceat(np.minimum(edges[:, 0], edges[:, 2]), first[:-1])
+    hi_x = np.maximum.reduceat(np.maximum(edges[:, 0], edges[:, 2]), first[:-1])
+    lo_y = np.minimum.reduceat(np.minimum(edges[:, 1], edges[:, 3]), first[:-1])
+    hi_y = np.maximum.reduceat(np.maximum(edges[:, 1], edges[:, 3]), first[:-1])
+    for t in pick:
+        z, x, y = (int(v) for v in tiles[t])
+        lon0, lon1, lat0, lat1 = _lonlat_box(z, x, y, 4.0)
+        sel = np.nonzero((hi_x >= lon0) & (lo_x <= lon1) & (hi_y >= lat0) & (lo_y <= lat1))[0]
+        got = unpack_masks(packed[t:t + 1])
+        if len(sel) == 0:
+            assert not got.any(), (what, t)
+            continue
+        sub = np.concatenate([edges[first[p]:first[p + 1]] for p in sel])
+        sub_first = np.concatenate([[0], np.cumsum(first[sel + 1] - first[sel])])
+        tri = oracle.OraclePolygons(sub, sub_first).render(tiles[t:t + 1])["tri"]
+        clean = tri != 2
+        bad = int((got[clean] != tri[clean]).sum())
+        log(f"{what} tile {tuple(tiles[t])}: polygons near={len(sel)} filled={int(got.sum())} "
+            f"ambiguous={int((~clean).sum())} mismatches={bad}")
+        assert bad == 0, (what, tuple(tiles[t]))
+
+
+def _fill(hv, torch, edges, first, tiles):
+    d = torch.from_numpy(edges).cuda()
+    torch.cuda.synchronize()
+    h = hv.hv_polygon_index_build(d, first)
+    del d
+    torch.cuda.empty_cache()
+    out = torch.empty((len(tiles), 8192), dtype=torch.uint8, device="cuda")
+    out.fill_(0x77)
+    hv.hv_render_fill(h, hv.tiles_array(tiles), out, None)
+    torch.cuda.synchronize()
+    hv.hv_free(h)
+    res = out.cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def test_c4_fill_full_size(hv, torch):
+    log("c4 fill full size: generate 2e8 edges")
+    edges = hvgen.gen_c4_edges()
+    first = hvgen.c4_polygon_first(edges)
+    tiles, _ = hvgen.c4_requests(edges, n=4096)
+    log(f"c4 fill full size: {len(first) - 1} polygons, 4096 requests")
+    full = _fill(hv, torch, edges, first, tiles)
+    # the fill of a set of polygons is the OR of the fills of any split of it
+    log("c4 fill full size: halves")
+    half = (len(first) - 1) // 2
+    a = _fill(hv, torch, edges[: first[half]], first[: half + 1], tiles)
+    b = _fill(hv, torch, edges[first[half]:], first[half:] - first[half], tiles)
+    assert np.array_equal(full, a | b), "whole set = OR of its halves"
+    assert full.any() and not full.all()
+    # deep tiles, and two at zoom 4-5 where regions hold thousands of polygons
+    low = np.nonzero((tiles[:, 0] >= 4) & (tiles[:, 0] <= 5))[0][:2]
+    pick = np.concatenate([_deep_sample(tiles, 6, zmin=8), low])
+    log(f"c4 fill full size: oracle on {len(pick)} sampled tiles")
+    _check_fill_sample(full, edges, first, tiles, pick, "c4-fill-full")
