@@ -285,7 +285,7 @@ hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *
  * launch: region mode only (region 32 or 64; NULL = region 32 with two
  * waves per workgroup, objs_per_lane 2, cand_cap 256, at any batch size).
  * Each region's candidate polygons are those whose bounding box holds one
- * of its pixel centres; their edges are tested in groups of up to 32
+ * of its pixel centres not filled yet; their edges are tested in groups of up to 32
  * polygons, and only the edges of 8-edge runs whose stored bounding box can
  * cross one of the region's pixel-centre rows are read.
  * Errors as hv_render_tiles_ex, plus HV_EINVAL for an index that is not a

@@ -946,6 +946,7 @@ constexpr int64_t kFillGrid = 262144;  // default workgroups of a filling launch
 struct FillLds {
     uint32_t *stk;
     uint32_t *cand;   // candidate polygons
+    uint32_t *crng;   // their pixel-centre ranges in the region: ilo | ihi << 6 | jlo << 12 | jhi << 18
     uint32_t *mask;   // RS rows x RS/32 words: filled so far
     uint32_t *par;    // kFillGroup x RS rows x RS/32 words: parity rows of the group (zero between groups)
     int64_t *efirst;  // edge range [efirst, eend) of each polygon of the group
@@ -958,7 +959,7 @@ struct FillLds {
 
 __host__ __device__ inline size_t fill_lds_bytes(int cap, int levels, int threads, int rs) {
     const size_t rows = (size_t)rs * (rs / 32) * 4;
-    return align16((size_t)region_stack_words(levels, threads) * 4) + align16((size_t)cap * 4) + align16(rows) +
+    return align16((size_t)region_stack_words(levels, threads) * 4) + 2 * align16((size_t)cap * 4) + align16(rows) +
            align16(kFillGroup * rows) + 2 * align16(kFillGroup * 8) + align16((kFillGroup + 1) * 8) +
            align16((size_t)threads * 8) + align16((size_t)threads) + 16;
 }
@@ -1018,7 +1019,10 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
             if (tid < 64) {  // edge ranges of the group and the prefix sums of their chunk counts
                 int64_t f = 0, fe = 0;
                 long long x = 0;
-                if (lane < nb) {
+                // a polygon whose pixel centres in the region are all filled
+                // already cannot change the fill: it gets no chunks
+                const uint32_t rg = lane < nb ? L.crng[c0 + lane] : 0u;
+                if (lane < nb && !range_lit<W>(mask, rg & 63, (rg >> 6) & 63, (rg >> 12) & 63, (rg >> 18) & 63)) {
                     const int64_t pid = L.cand[c0 + lane];
                     f = ix.pfirst[pid];
                     fe = ix.pfirst[pid + 1];
@@ -1131,24 +1135,45 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
         if (lvl > 0) {
             const int cl = lvl - 1;
             const int64_t child = (int64_t)node * kFan + c;
-            const bool push = j < npop && child < ix.meta[kMaxLevels + cl] &&
-                              meets(ix.nodes[ix.meta[cl] + child], qx0, qx1, qy0, qy1);
+            bool push = false;
+            if (j < npop && child < ix.meta[kMaxLevels + cl]) {
+                const double4 nb = ix.nodes[ix.meta[cl] + child];
+                if (meets(nb, qx0, qx1, qy0, qy1)) {
+                    // the same test as for a polygon below: the node's box
+                    // holds every box of its subtree, and its range of pixel
+                    // centres (rounded the same way) every range of theirs
+                    const double cx0 = fmax(ceil(nb.x * S - ox - i0 - 0.5), 0.0);
+                    const double cx1 = fmin(floor(nb.z * S - ox - i0 - 0.5), RS - 1.0);
+                    const double cy0 = fmax(ceil(nb.y * S - oy - j0 - 0.5), 0.0);
+                    const double cy1 = fmin(floor(nb.w * S - oy - j0 - 0.5), RS - 1.0);
+                    push = cx0 <= cx1 && cy0 <= cy1 &&
+                           !range_lit<W>(mask, (int)cx0, (int)cx1, (int)cy0, (int)cy1);
+                }
+            }
             const int pos = wave_alloc(&ctl[0], __ballot(push), lane);
             if (push) stk[pos] = ((uint32_t)cl << kLevelShift) | (uint32_t)child;
         } else {
-            // a polygon whose box holds no pixel centre of the region holds none
+            // a polygon whose box holds no pixel centre of the region holds
+            // none, and one whose centres are all filled adds nothing
             const int64_t o = (int64_t)node * kLeaf + c;
             bool keep = false;
+            uint32_t rg = 0;
             if (j < npop && o < ix.n) {
                 const double4 bb = reinterpret_cast<const double4 *>(ix.obj)[o];
                 const double cx0 = fmax(ceil(bb.x * S - ox - i0 - 0.5), 0.0);
                 const double cx1 = fmin(floor(bb.z * S - ox - i0 - 0.5), RS - 1.0);
                 const double cy0 = fmax(ceil(bb.y * S - oy - j0 - 0.5), 0.0);
                 const double cy1 = fmin(floor(bb.w * S - oy - j0 - 0.5), RS - 1.0);
-                keep = cx0 <= cx1 && cy0 <= cy1;
+                if (cx0 <= cx1 && cy0 <= cy1) {
+                    rg = (uint32_t)cx0 | ((uint32_t)cx1 << 6) | ((uint32_t)cy0 << 12) | ((uint32_t)cy1 << 18);
+                    keep = !range_lit<W>(mask, (int)cx0, (int)cx1, (int)cy0, (int)cy1);
+                }
             }
             const int slot = wave_alloc(&ctl[1], __ballot(keep), lane);
-            if (keep) L.cand[slot] = (uint32_t)o;  // edges and offsets are stored by sorted position
+            if (keep) {
+                L.cand[slot] = (uint32_t)o;  // edges and offsets are stored by sorted position
+                L.crng[slot] = rg;
+            }
         }
         __syncthreads();
         if (ctl[1] > cap - nthr && test()) {
@@ -1175,7 +1200,8 @@ __global__ __launch_bounds__(256) void k_fill_region(DevBatch B, int cap, int ma
     unsigned char *cb = base + align16((size_t)region_stack_words(max_levels, blockDim.x) * 4);
     constexpr size_t kRows = (size_t)RS * (RS / 32) * 4;
     L.cand = reinterpret_cast<uint32_t *>(cb);
-    L.mask = reinterpret_cast<uint32_t *>(cb + align16((size_t)cap * 4));
+    L.crng = reinterpret_cast<uint32_t *>(cb + align16((size_t)cap * 4));
+    L.mask = reinterpret_cast<uint32_t *>(cb + 2 * align16((size_t)cap * 4));
     L.par = L.mask + align16(kRows) / 4;
     L.efirst = reinterpret_cast<int64_t *>(L.par + align16(kFillGroup * kRows) / 4);
     L.eend = L.efirst + align16(kFillGroup * 8) / 8;
