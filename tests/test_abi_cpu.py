@@ -160,3 +160,42 @@ def test_polygon_index_validation_before_any_device_call(hv):
             hv.hv_render_fill(p, [(0, 0, 0)], 1)
     finally:
         hv.hv_free(p)
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include <string.h>
+#include "hv.h"
+
+int main(void) {
+    /* an empty index needs no device; bad requests fail on the host */
+    hv_index *ix = hv_index_build(NULL, HV_POINTS, 0);
+    if (!ix) { printf("build failed: %s\n", hv_last_error()); return 1; }
+    hv_info info;
+    if (hv_index_info(ix, &info) != HV_OK || info.n != 0) return 2;
+    hv_tile bad = {23, 0, 0, 0};
+    hv_style st = {1.0};
+    if (hv_render_tiles(ix, &bad, 1, &st, NULL) != HV_EINVAL) return 3;
+    if (strlen(hv_last_error()) == 0) return 4;
+    hv_launch L;
+    memset(&L, 0, sizeof L);
+    L.cull_nodes = 300;
+    if (hv_render_tiles_ex(ix, &bad, 0, &st, NULL, &L) != HV_EINVAL) return 5;
+    hv_free(ix);
+    printf("c-abi ok\n");
+    return 0;
+}
+"""
+
+
+def test_header_compiles_as_c99_and_links(hv, tmp_path):
+    """include/hv.h is plain C: a C99 program compiles against it with
+    -Wall -Werror, links against the library, and runs its host-only paths."""
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(hv.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe), f"-L{libdir}", "-l:libhv.so", f"-Wl,-rpath,{libdir}"], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and "c-abi ok" in out.stdout, (out.returncode, out.stdout, out.stderr)
