@@ -798,11 +798,17 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         }
                     }
                     if (push && range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
-                    // The accept pass stops at leaves and at nodes no wider than
-                    // racc: nodes of that size, spread over an area, light every
-                    // pixel centre of it.  It enters a larger node only if its
-                    // leaves, at about 4^-level of its size, could be small.
-                    if (accept_pass && push && (diag2 <= racc2 || cl == 0 || diag2 > ldexp(16.0 * racc2, 4 * cl)))
+                    // The accept pass stops at leaves and at nodes whose diagonal
+                    // is at most 1.5 racc.  A box's edge accepts light every pixel
+                    // centre inside it once its diagonal is at most 2 racc (the
+                    // centre of the box is the farthest from the ends of its
+                    // edges, at half the diagonal), so such nodes, spread over an
+                    // area, light all of it; stopping well below 2 racc keeps the
+                    // accepts of their children for the ring of pixels around
+                    // them, which would otherwise fall to the full walk.  It
+                    // enters a larger node only if its leaves, at about
+                    // 4^-level of its size, could be small.
+                    if (accept_pass && push && (diag2 <= 2.25 * racc2 || cl == 0 || diag2 > ldexp(16.0 * racc2, 4 * cl)))
                         push = false;
                 }
             }
