@@ -121,10 +121,12 @@ int hv_set_stream(void *hip_stream);
  * the batch size n: region = 32, objs_per_lane 2, waves_per_wg 4 for
  * n < 1024, 2 for n < 4096 and 1 beyond (in a small batch the heaviest
  * regions set the time and more waves shorten them; a large one fills the
- * GPU with single-wave groups), and cand_cap 128 * waves_per_wg.  For
- * anti-aliased output n counts the 4 children of each request.  In a given shape, zero fields take block 16, waves_per_wg 2 (1 in
- * region mode), objs_per_lane 1, cand_cap 64 * waves_per_wg * objs_per_lane
- * in region mode (64 otherwise) and a grid that fills the GPU; region = 0
+ * GPU with single-wave groups), cand_cap 128 * waves_per_wg and cull_nodes
+ * 256.  For anti-aliased output n counts the 4 children of each request;
+ * filling has its own default (hv_render_fill).  In a given shape, zero
+ * fields take block 16, waves_per_wg 2 (1 in region mode), objs_per_lane
+ * 1, cand_cap 64 * waves_per_wg * objs_per_lane in region mode (64
+ * otherwise), cull_nodes 256 and a grid that fills the GPU; region = 0
  * selects one wavefront per pixel block. */
 typedef struct {
     int32_t block;          /* pixel block per wavefront: 8, 16 or 32 (1, 4 or 16 px/lane) */
