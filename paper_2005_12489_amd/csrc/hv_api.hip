@@ -689,10 +689,13 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     // and one wave per block (side, waves, stage capacity); the default's
     // three shapes first (region queues at their minimum, 64 x waves x
     // objects per lane: larger queues cost occupancy)
-    // (the last field, cull depth, 0 = 256 frontier nodes)
+    // (the last field, cull depth, 0 = 256 frontier nodes; grid 2^20 gives
+    // each region its own workgroup, which helps batches whose regions
+    // differ widely in cost)
     static const hv_launch cands[] = {
         {0, 128, 1, 0, 32, 2, 0}, {0, 256, 2, 0, 32, 2, 0}, {0, 512, 4, 0, 32, 2, 0}, {0, 128, 1, 0, 32, 2, 128},
-        {0, 128, 1, 0, 32, 2, 32}, {0, 512, 4, 0, 32, 2, 32}, {0, 64, 1, 0, 32, 1}, {0, 256, 1, 0, 32, 4},
+        {0, 128, 1, 0, 32, 2, 32}, {0, 512, 4, 0, 32, 2, 32}, {0, 128, 1, 1 << 20, 32, 2, 0},
+        {0, 64, 1, 0, 32, 1}, {0, 256, 1, 0, 32, 4},
         {0, 128, 2, 0, 32, 1}, {0, 256, 4, 0, 32, 1}, {0, 128, 1, 0, 64, 2}, {0, 256, 2, 0, 64, 2},
         {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},
         {16, 128, 4, 0, 0, 1}, {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},
