@@ -945,7 +945,8 @@ __global__ __launch_bounds__(256) void k_query_region(DevBatch B, int cap, int m
 // own parity rows, and the rows are ORed into the fill after the group.  A
 // chunk's conservative box decides whether any of its edges can cross a row
 // centre line of the region left of its last pixel centre; only then are its
-// edges read.
+// edges read.  A polygon (or a subtree) whose pixel centres in the region are
+// all filled already cannot change the OR and is skipped.
 constexpr int kFillGroup = 32;
 constexpr int64_t kFillGrid = 262144;  // default workgroups of a filling launch (at most one per region)
 
