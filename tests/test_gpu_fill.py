@@ -161,6 +161,39 @@ def test_fill_star_polygons_mixed_zooms(hv, torch):
     hv.hv_free(h)
 
 
+def test_fill_degenerate_geometry(hv, torch):
+    """Degenerate rings placed on pixel-centre lines (tile-local px, centres
+    at k + 0.5): zero-length edges, collinear vertices, edges along row and
+    column centre lines, a bow-tie, two polygons sharing an edge, a hole
+    touching its outer ring, a sliver thinner than 1e-9 px along a row line,
+    and an 8000-edge ring spanning many edge chunks."""
+    z, x, y = 12, 1500, 1700
+    box = _box
+    polys = [
+        [[(10.5, 10.5), (10.5, 10.5), (20.5, 10.5), (25.5, 10.5), (30.5, 10.5), (30.5, 20.5), (10.5, 20.5)]],
+        [box(40.0, 40.5, 60.0, 50.5)],                                        # top and bottom edges on row lines
+        [box(70.5, 40.0, 80.5, 60.0)],                                        # left and right edges on column lines
+        [[(100.0, 100.0), (120.0, 120.0), (120.0, 100.0), (100.0, 120.0)]],   # bow-tie
+        [box(140.0, 100.0, 150.0, 110.0)], [box(150.0, 100.0, 160.0, 110.0)],  # shared edge x = 150
+        [box(10.0, 140.0, 40.0, 170.0), [(10.0, 140.0), (20.0, 150.0), (30.0, 140.0)]],  # hole touching the ring
+        [[(60.0, 150.5 - 1e-10), (90.0, 150.5 - 1e-10), (90.0, 150.5 + 1e-10), (60.0, 150.5 + 1e-10)]],  # sliver
+    ]
+    k = 8000
+    ang = np.linspace(0.0, 2.0 * math.pi, k, endpoint=False)
+    rad = 60.0 + 25.0 * np.sin(7.0 * ang)
+    polys.append([[(190.0 + rad[q] * math.cos(ang[q]) * 0.8, 200.0 + rad[q] * math.sin(ang[q]) * 0.8) for q in range(k)]])
+    e, f = _group(polys, z, x, y)
+    h = build_polys(hv, torch, e, f, merc01=True)
+    tiles = [(z, x, y), (z, x + 1, y), (z, x, y + 1), (z - 1, x // 2, y // 2), (z + 1, 2 * x, 2 * y)]
+    log("fill degenerate geometry")
+    ref = oracle.OraclePolygons(e, f, merc01=True).render(tiles)["tri"]
+    got = fill(hv, torch, h, tiles)
+    check(got, ref, "fill degenerate geometry")
+    for L in (dict(region=64, waves_per_wg=4, cand_cap=256), dict(region=32, waves_per_wg=1, cand_cap=128, cull_nodes=1)):
+        assert np.array_equal(fill(hv, torch, h, tiles, L), got), L
+    hv.hv_free(h)
+
+
 def test_fill_empty_index_and_far_tiles(hv, torch):
     e = hv.hv_polygon_index_build(None, [0])
     got = fill(hv, torch, e, [(0, 0, 0), (7, 3, 100)])
