@@ -685,20 +685,20 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     const BatchPlan &p = plans[kStages - 1];
     int rc = HV_OK;
     if ((rc = validate_out(scratch_masks))) return rc;
-    // candidate shapes: region mode (side, waves, objects per lane, queue)
-    // and one wave per block (side, waves, stage capacity); the default's
-    // three shapes first (region queues at their minimum, 64 x waves x
-    // objects per lane: larger queues cost occupancy)
-    // (the last field, cull depth, 0 = 256 frontier nodes; grid 2^20 gives
-    // each region its own workgroup, which helps batches whose regions
-    // differ widely in cost)
+    // Candidate shapes, all in region mode: side, waves, objects per lane,
+    // queue, and the cull depth in the last field (0 = 256 frontier nodes).
+    // The default's three shapes come first (queues at their minimum, 64 x
+    // waves x objects per lane: larger queues cost occupancy); grid 2^20
+    // gives each region its own workgroup, which helps batches whose regions
+    // differ widely in cost.  One wavefront per pixel block (region 0) is
+    // not a candidate: it never won, and without the accept pass a single
+    // run of it on a few dense low-zoom tiles can take seconds.
     static const hv_launch cands[] = {
         {0, 128, 1, 0, 32, 2, 0}, {0, 256, 2, 0, 32, 2, 0}, {0, 512, 4, 0, 32, 2, 0}, {0, 128, 1, 0, 32, 2, 128},
         {0, 128, 1, 0, 32, 2, 32}, {0, 512, 4, 0, 32, 2, 32}, {0, 128, 1, 1 << 20, 32, 2, 0},
         {0, 64, 1, 0, 32, 1}, {0, 256, 1, 0, 32, 4},
         {0, 128, 2, 0, 32, 1}, {0, 256, 4, 0, 32, 1}, {0, 128, 1, 0, 64, 2}, {0, 256, 2, 0, 64, 2},
-        {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2}, {16, 64, 2, 0, 0, 1},  {16, 64, 1, 0, 0, 1},
-        {16, 128, 4, 0, 0, 1}, {8, 64, 2, 0, 0, 1},   {8, 64, 4, 0, 0, 1},   {32, 64, 1, 0, 0, 1},
+        {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2},
     };
     // events around the two kernels only: staging and the workspace
     // allocation are the same for every shape and only add noise
