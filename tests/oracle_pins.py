@@ -250,6 +250,105 @@ def pin_brute(lib_path=None, n_obj=160, seed=13):
     _check_against_brute(out, 0, m, 0, tile, 1.5)
 
 
+# ------------------------------------------------------------ work counters
+# Per tile the oracle counts C_LIT (pixels with D <= r), C_NBOX_UNLIT (the sum
+# over unlit pixels p of N_box(p), the objects whose bounding box meets p's
+# c +- r box) and C_UNLIT_CAND (distinct objects whose box meets the c +- r
+# box of some unlit pixel).  They give the algorithmic bytes and flops of the
+# roofline, so they are pinned like the masks: closed forms and a brute force.
+def _cnt(out, t=0):
+    c = out["counters"][t]
+    return (int(c[oracle.C_LIT]), int(c[oracle.C_AMB]), int(c[oracle.C_NBOX_UNLIT]),
+            int(c[oracle.C_UNLIT_CAND]))
+
+
+def pin_cnt_closed_forms(lib_path=None):
+    z, x, y = 10, 300, 400
+    t = [[z, x, y]]
+
+    def pts(offsets, r):
+        P = [_px_to_merc(z, x, y, u, v) for u, v in offsets]
+        return _cnt(_ix(P, oracle.POINTS, lib_path=lib_path).render(t, r, want_counters=True))
+
+    # One point on a pixel centre, r = 2: integer offsets (a, b) with |a|, |b| <= 2
+    # put the point in the pixel's box (25 pixels); a^2 + b^2 <= 4 lights 13 of
+    # them (4 exactly at 2: ambiguous, lit by the inclusive bit); the other 12
+    # are unlit with one object in their box.
+    assert pts([(100.5, 50.5)], 2.0) == (13, 4, 12, 1), pts([(100.5, 50.5)], 2.0)
+    # On a pixel corner: half-integer offsets, 4 x 4 pixels in the box, 12 lit.
+    assert pts([(100.0, 50.0)], 2.0) == (12, 0, 4, 1), pts([(100.0, 50.0)], 2.0)
+    # Two far-apart points: everything doubles, two distinct candidates.
+    assert pts([(100.5, 50.5), (200.5, 150.5)], 2.0) == (26, 8, 24, 2)
+    # Two coincident points: each is its own object, each must be read.
+    assert pts([(100.5, 50.5), (100.5, 50.5)], 2.0) == (13, 4, 24, 2)
+    # A point 2^-18 px east of a pixel centre, r = 2: offsets a in {-1..2},
+    # |b| <= 2 keep it in the pixel's c +- r box (20 pixels; a = -2 misses by
+    # 2^-18 px, although the query box c +- (r + 1e-5) still meets it).  Lit:
+    # b = 0 with a in {-1..2}, |b| = 1 with a in {-1, 0, 1}: 10.  (0, +-2) lie
+    # 2^-38 px beyond r: ambiguous and unlit.  Unlit in the box: 10.
+    d = 2.0 ** -18
+    assert pts([(100.5 + d, 50.5)], 2.0) == (10, 2, 10, 1), pts([(100.5 + d, 50.5)], 2.0)
+    # Far from every pixel of the tile: nothing lit, nothing in any box.
+    assert pts([(-40.5, 50.5)], 2.0) == (0, 0, 0, 0)
+    # A horizontal segment through the centres of row j, columns a..b (L pixels).
+    a, b, j = 20, 60, 77
+    L = b - a + 1
+    ix = _ix(_seg(z, x, y, a + 0.5, j + 0.5, b + 0.5, j + 0.5), oracle.SEGMENTS, lib_path=lib_path)
+    # r = 1/2: its box meets the c +- 1/2 boxes of row j, columns a..b only
+    # (the end neighbours' boxes stop at x = a, short of the end at a + 1/2),
+    # and all of those are lit: no unlit pixel needs it.
+    assert _cnt(ix.render(t, 0.5, want_counters=True)) == (L, 0, 0, 0)
+    # r = 1: rows j-1..j+1, columns a-1..b+1; lit: 3L + 2 (2L + 2 exactly at
+    # 1); the four corners at sqrt(2) are the unlit ones.
+    assert _cnt(ix.render(t, 1.0, want_counters=True)) == (3 * L + 2, 2 * L + 2, 4, 1)
+
+
+def _brute_counters(objs, kind, z, x, y, r):
+    """(C_LIT, C_NBOX_UNLIT, C_UNLIT_CAND, near ties) by enumeration: every
+    pixel's c +- r box against every object's box, in tile-local pixels."""
+    S = 256.0 * 2.0 ** z
+    o = np.asarray(objs, dtype=np.float64).reshape(-1, 2 if kind == 0 else 4)
+    if kind == 0:
+        o = np.concatenate([o, o], 1)
+    u0, u1 = o[:, 0] * S - 256.0 * x, o[:, 2] * S - 256.0 * x
+    v0, v1 = o[:, 1] * S - 256.0 * y, o[:, 3] * S - 256.0 * y
+    bx0, bx1 = np.minimum(u0, u1), np.maximum(u0, u1)
+    by0, by1 = np.minimum(v0, v1), np.maximum(v0, v1)
+    c = np.arange(256, dtype=np.float64) + 0.5
+    # per axis: does object k's interval meet pixel column / row i's [c - r, c + r]
+    mx = (bx0[:, None] <= c[None, :] + r) & (bx1[:, None] >= c[None, :] - r)     # (n, 256) columns
+    my = (by0[:, None] <= c[None, :] + r) & (by1[:, None] >= c[None, :] - r)     # (n, 256) rows
+    gaps = np.concatenate([np.abs(bx0[:, None] - (c + r)), np.abs(bx1[:, None] - (c - r)),
+                           np.abs(by0[:, None] - (c + r)), np.abs(by1[:, None] - (c - r))])
+    near = int((gaps < 1e-9).sum())
+    D = brute_distance(objs, kind if kind == 0 else 1, z, x, y)
+    unlit = D > r
+    nbox = np.einsum("kj,ki->ji", my.astype(np.int64), mx.astype(np.int64))   # (row, column)
+    hit = np.einsum("kj,ki,ji->k", my.astype(np.int64), mx.astype(np.int64), unlit.astype(np.int64))
+    return int((~unlit).sum()), int(nbox[unlit].sum()), int((hit > 0).sum()), near + int(near_band_edge(D, r).sum())
+
+
+def pin_cnt_brute(lib_path=None, n_obj=120, seed=17):
+    rng = np.random.default_rng(seed)
+    for kind in (oracle.POINTS, oracle.SEGMENTS):
+        for z in (4, 13):
+            x = int(rng.integers(1, (1 << z) - 1))
+            y = int(rng.integers(1, (1 << z) - 1))
+            objs = _random_objects(rng, kind, z, x, y, n_obj)
+            # clustered copies too, so that several objects meet one pixel's box
+            objs = np.concatenate([objs, objs[:20] + rng.normal(0, 1.0 / (256 * 2.0 ** z), objs[:20].shape)])
+            ix = _ix(objs, kind, lib_path=lib_path)
+            tiles = [(z, x, y), (z, x - 1, y + 1)]
+            rs = (0.7, 2.5)
+            out = ix.render(np.array(tiles), np.array(rs), want_counters=True)
+            for t, tile in enumerate(tiles):
+                lit, nbox, cand, near = _brute_counters(objs, kind, *tile, rs[t])
+                assert near == 0, ("choose another seed: a box edge or distance is within 1e-9 px", tile)
+                got = _cnt(out, t)
+                assert (got[0], got[2], got[3]) == (lit, nbox, cand), (kind, tile, rs[t], got, (lit, nbox, cand))
+                assert cand <= len(objs) and (nbox == 0) == (cand == 0)
+
+
 # ------------------------------------------------------------ cKDTree
 def pin_ckdtree(lib_path=None, n_tiles=256):
     from scipy.spatial import cKDTree
@@ -531,4 +630,6 @@ PINS = {
     "fill_closed_forms": pin_fill_closed_forms,
     "fill_brute": pin_fill_brute,
     "fill_invariants": pin_fill_invariants,
+    "cnt_closed_forms": pin_cnt_closed_forms,
+    "cnt_brute": pin_cnt_brute,
 }

@@ -47,6 +47,14 @@ MUTANTS = [
     ("fill-first-polygon-only", "for (int32_t c = 0; c < M->count[nd] && !inside_sure; ++c) {",
      "for (int32_t c = 0; c < M->count[nd] && c < 1; ++c) {"),
     ("fill-box-min-y", "y0 = fmin(y0, fmin(P->ay[q], P->by[q]));", "y0 = fmin(y0, fmax(P->ay[q], P->by[q]));"),
+    # work counters (the roofline's algorithmic bytes and flops)
+    ("cnt-widened-box", "if (box_meets(&b, &qr)) {", "if (box_meets(&b, &q)) {"),
+    ("cnt-duplicates", "uniq += sc->tile_ids[q] != sc->tile_ids[q - 1];", "uniq += 1;"),
+    ("cnt-lit-pixels-too", "if (!b) {\n                nbox_unlit", "if (1) {\n                nbox_unlit"),
+    ("cnt-lit-certain-only", "lit += b;", "lit += (t == 1);"),
+    ("cnt-box-half-height", "obox qr = { (cx - r) / S, (cy - r) / S, (cx + r) / S, (cy + r) / S };",
+     "obox qr = { (cx - r) / S, (cy - r) / S, (cx + r) / S, cy / S };"),
+    ("cnt-unlit-ambiguous-only", "if (!b) {\n                nbox_unlit", "if (t == 0) {\n                nbox_unlit"),
 ]
 
 
@@ -59,6 +67,6 @@ def test_mutant_is_caught(name, old, new, tmp_path):
     sys.path.insert(0, ROOT)
     from oracle import build as ob
     lib = ob.build(str(mut), str(tmp_path / "libmut.so"))
-    family = name.split("-")[0] + "_" if name.startswith(("aa-", "fill-")) else ""
+    family = name.split("-")[0] + "_" if name.startswith(("aa-", "fill-", "cnt-")) else ""
     res = subprocess.run([sys.executable, RUNNER, lib, family], capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"planted mistake {name!r} was not caught:\n{res.stdout}{res.stderr}"
