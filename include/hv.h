@@ -296,6 +296,26 @@ hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *
 int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
                    const hv_launch *launch);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Renders a
+ * batch exactly as hv_render_batch does (same arguments, kernels and masks)
+ * but calls no allocating routine: the batch's device workspace lives in a
+ * static device array of the library (5 MiB on each device the library runs
+ * on, held until the process ends) and its host staging in static host
+ * memory.  Limits: n <= HV_NOALLOC_MAX_REQUESTS requests over at most
+ * HV_NOALLOC_MAX_INDEXES distinct indexes; larger batches are rejected with
+ * HV_EINVAL before any device call.  All calls on one device share that
+ * array: calls are serialised on the host, and the copy of each call's
+ * requests is ordered after earlier work on the calling thread's stream, so
+ * consecutive calls on one stream are safe, but calls on different streams
+ * of one device whose kernels overlap race on the array.  The call waits
+ * until its requests have reached the device (a stream synchronisation);
+ * the kernels then run asynchronously on the calling thread's stream.
+ * Errors as hv_render_batch. */
+#define HV_NOALLOC_MAX_REQUESTS 4096
+#define HV_NOALLOC_MAX_INDEXES 16
+int hv_render_batch_noalloc(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch);
+
 /* Kernel timing for roofline figures.  Renders the batch reps times, as
  * hv_render_batch would (same arguments; launch NULL takes the tuned shape
  * or the default), each time recording HIP events on the calling thread's

@@ -259,25 +259,28 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::vector<std::pair<TuneKey, hv_launch>> g_tune;
 
-TuneKey batch_key(const hv_request *reqs, int64_t n) {
+// zs, rs: host scratch of n entries each (the medians are taken in place).
+TuneKey batch_key_in(const hv_request *reqs, int64_t n, int *zs, double *rs) {
     int64_t seg = 0;
-    std::vector<int> zs((size_t)n);
-    std::vector<double> rs((size_t)n);
     for (int64_t k = 0; k < n; ++k) {
         seg += reqs[k].index->kind != HV_POINTS;
-        zs[(size_t)k] = reqs[k].z;
-        rs[(size_t)k] = reqs[k].r_px;
+        zs[k] = reqs[k].z;
+        rs[k] = reqs[k].r_px;
     }
-    std::nth_element(zs.begin(), zs.begin() + n / 2, zs.end());
-    std::nth_element(rs.begin(), rs.begin() + n / 2, rs.end());
-    const double rm = rs[(size_t)(n / 2)];
-    return TuneKey{seg * 2 >= n ? 1 : 0, zs[(size_t)(n / 2)] / 4, rm <= 1.0 ? 0 : rm <= 2.0 ? 1 : rm <= 4.0 ? 2 : 3,
+    std::nth_element(zs, zs + n / 2, zs + n);
+    std::nth_element(rs, rs + n / 2, rs + n);
+    const double rm = rs[n / 2];
+    return TuneKey{seg * 2 >= n ? 1 : 0, zs[n / 2] / 4, rm <= 1.0 ? 0 : rm <= 2.0 ? 1 : rm <= 4.0 ? 2 : 3,
                    default_waves(n)};
 }
 
-bool tuned_for(const hv_request *reqs, int64_t n, hv_launch *out) {
-    if (n <= 0) return false;
-    const TuneKey key = batch_key(reqs, n);
+TuneKey batch_key(const hv_request *reqs, int64_t n) {
+    std::vector<int> zs((size_t)n);
+    std::vector<double> rs((size_t)n);
+    return batch_key_in(reqs, n, zs.data(), rs.data());
+}
+
+bool tuned_for_key(const TuneKey &key, hv_launch *out) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     for (auto &e : g_tune)
         if (e.first == key) {
@@ -285,6 +288,11 @@ bool tuned_for(const hv_request *reqs, int64_t n, hv_launch *out) {
             return true;
         }
     return false;
+}
+
+bool tuned_for(const hv_request *reqs, int64_t n, hv_launch *out) {
+    if (n <= 0) return false;
+    return tuned_for_key(batch_key(reqs, n), out);
 }
 
 }  // namespace
@@ -942,6 +950,121 @@ int hv_batcher_latency(hv_batcher *b, double *latency_us, int64_t n) {
 
 void hv_batcher_free(hv_batcher *b) {
     if (b) batcher_release(b);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- no allocation
+// hv_render_batch_noalloc runs the kernels of hv_render_batch on a batch
+// workspace held in `scratch`, a file-scope device array, instead of a
+// stream-ordered allocation.  Each device holds its own copy of the array for
+// the life of the process; its address on a device is looked up once, with
+// that device current, and kept in g_scratch_dev.  Host code never uses the
+// array's name as an address (on the host it only names the symbol).
+// The workspace's counters start at zero because the staged header copied in
+// by every call holds them; everything else in it is written by the kernels
+// before it is read.
+namespace {
+constexpr size_t kScratchBytes = size_t(5) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_noalloc_mu;                    // guards everything below
+void *g_scratch_dev[kMaxDevices] = {};      // per device: the address of its `scratch`
+// host staging of one call: the staged part of the workspace, the requests in
+// kernel form, and the medians' scratch of the tuned-shape lookup
+alignas(256) unsigned char g_noalloc_host[size_t(128) << 10];
+hv::DevReq g_noalloc_reqs[HV_NOALLOC_MAX_REQUESTS];
+int g_noalloc_z[HV_NOALLOC_MAX_REQUESTS];
+double g_noalloc_r[HV_NOALLOC_MAX_REQUESTS];
+
+// The address of `scratch` on device dev (current); looked up on first use.
+int scratch_on(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(HV_EINVAL, "hv_render_batch_noalloc: device ordinal above 63");
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e, "hv_render_batch_noalloc: hipGetSymbolAddress(scratch)");
+        if (!p) return fail(HV_EHIP, "hv_render_batch_noalloc: hipGetSymbolAddress(scratch) gave NULL");
+        g_scratch_dev[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_dev[dev]);
+    return HV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hv_render_batch_noalloc(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch) {
+    if (n < 0) return fail(HV_EINVAL, "n < 0");
+    if (n > HV_NOALLOC_MAX_REQUESTS)
+        return fail(HV_EINVAL, "n = " + std::to_string(n) + " exceeds HV_NOALLOC_MAX_REQUESTS (" +
+                                   std::to_string(HV_NOALLOC_MAX_REQUESTS) + "), the static scratch's capacity");
+    if (n > 0 && !reqs) return fail(HV_EINVAL, "reqs is NULL with n > 0");
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    // validation and the index table, as plan_batch does, into static storage
+    hv::DevIndex table[HV_NOALLOC_MAX_INDEXES];
+    const hv_index *owners[HV_NOALLOC_MAX_INDEXES];
+    int n_ix = 0, max_levels = 0, dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_status(hipGetLastError(), "hipGetDevice");
+    for (int64_t k = 0; k < n; ++k) {
+        const hv_request &q = reqs[k];
+        if (!q.index) return fail(HV_EINVAL, "request " + std::to_string(k) + ": index is NULL");
+        if (q.index->kind == HV_POLYGONS)
+            return fail(HV_EINVAL, "request " + std::to_string(k) + ": a polygon index renders with hv_render_fill");
+        int rc = validate_tile(q.z, q.x, q.y, k);
+        if (rc) return rc;
+        if ((rc = validate_r(q.r_px, k))) return rc;
+        int slot = -1;
+        for (int j = n_ix - 1; j >= 0; --j)
+            if (owners[j] == q.index) {
+                slot = j;
+                break;
+            }
+        if (slot < 0) {
+            if (q.index->device >= 0 && q.index->device != dev)
+                return fail(HV_EINVAL, "request " + std::to_string(k) + ": index lives on another device");
+            if (n_ix == HV_NOALLOC_MAX_INDEXES)
+                return fail(HV_EINVAL, "the batch names more than HV_NOALLOC_MAX_INDEXES (" +
+                                           std::to_string(HV_NOALLOC_MAX_INDEXES) + ") indexes");
+            slot = n_ix++;
+            owners[slot] = q.index;
+            table[slot] = dev_view(q.index);
+            if (q.index->a.levels > max_levels) max_levels = q.index->a.levels;
+        }
+        g_noalloc_reqs[k] = hv::DevReq{q.z, q.x, q.y, slot, q.r_px};
+    }
+    hv_launch tuned;
+    if (!launch && n > 0 && tuned_for_key(batch_key_in(reqs, n, g_noalloc_z, g_noalloc_r), &tuned)) launch = &tuned;
+    hv::LaunchShape shape;
+    int rc = resolve_shape(launch, max_levels, &shape, n);
+    if (rc) return rc;
+    if (n == 0) {
+        t_err.clear();
+        return HV_OK;
+    }
+    if ((rc = validate_out(out_masks))) return rc;
+    const hv::Workspace w = hv::workspace_layout(n, n_ix);
+    if (w.total > kScratchBytes || w.staged_bytes() > sizeof(g_noalloc_host))
+        return fail(HV_EINVAL, "hv_render_batch_noalloc: the batch's workspace exceeds the static scratch");
+    unsigned char *ws = nullptr;
+    if ((rc = scratch_on(dev, &ws))) return rc;
+    hv::stage_host(w, table, n_ix, g_noalloc_reqs, n, out_masks, g_noalloc_host);
+    // The staged bytes travel from pageable static memory; the wait makes sure
+    // the copy has read them before the next call may overwrite them.  The
+    // copy is ordered after earlier work on this stream, so a call never
+    // overwrites a workspace that an earlier call on the same stream still uses.
+    hipError_t e = hipMemcpyAsync(ws, g_noalloc_host, w.staged_bytes(), hipMemcpyHostToDevice, t_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(t_stream);
+    if (e == hipSuccess) e = hv::launch_query(w, ws, max_levels, shape, t_stream);
+    if (e != hipSuccess) return hip_status(e, "hv_render_batch_noalloc");
+    t_err.clear();
+    return HV_OK;
 }
 
 }  // extern "C"

@@ -38,11 +38,14 @@ HV_READ_ORDER, HV_READ_OBJECTS, HV_READ_NODES = 0, 1, 2
 HV_MASK_BYTES = 8192
 HV_AA_BYTES = 65536
 HV_MAX_ZOOM = 22
+HV_NOALLOC_MAX_REQUESTS = 4096
+HV_NOALLOC_MAX_INDEXES = 16
 
 SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free", "hv_last_error",
            "hv_set_stream", "hv_index_info", "hv_index_read", "hv_render_batch", "hv_batcher_create",
            "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch",
-           "hv_time_kernels", "hv_render_batch_aa", "hv_polygon_index_build", "hv_render_fill")
+           "hv_time_kernels", "hv_render_batch_aa", "hv_polygon_index_build", "hv_render_fill",
+           "hv_render_batch_noalloc")
 
 # hv_request as a numpy record (32 bytes, the C layout)
 REQUEST_DTYPE = np.dtype([("index", np.uint64), ("z", np.int32), ("x", np.int32), ("y", np.int32),
@@ -102,6 +105,8 @@ lib.hv_index_read.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64
 
 lib.hv_render_batch.restype = ctypes.c_int
 lib.hv_render_batch.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
+lib.hv_render_batch_noalloc.restype = ctypes.c_int
+lib.hv_render_batch_noalloc.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
 lib.hv_batcher_create.restype = _P
 lib.hv_batcher_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(hv_launch)]
 lib.hv_batcher_run.restype = ctypes.c_int
@@ -268,6 +273,16 @@ def hv_render_batch(reqs, out_masks, launch=None) -> None:
     _sync_stream()
     _check(lib.hv_render_batch(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks),
                                ctypes.byref(L) if L else None))
+
+
+def hv_render_batch_noalloc(reqs, out_masks, launch=None) -> None:
+    """hv_render_batch on the library's static device scratch (no allocation);
+    at most HV_NOALLOC_MAX_REQUESTS requests over HV_NOALLOC_MAX_INDEXES indexes."""
+    r = _reqs(reqs)
+    L = _launch(launch)
+    _sync_stream()
+    _check(lib.hv_render_batch_noalloc(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks),
+                                       ctypes.byref(L) if L else None))
 
 
 def hv_polygon_index_build(edges, first, flags: int = 0) -> int:
