@@ -5,13 +5,14 @@ HIP graph [copy the staged requests -> tile-frontier kernel -> query kernel]
 replayed by hv_batcher, with the index already resident in HBM.
 
 Workloads (--workload):
-  c2 (default)  10,000,000 linestring segments (random-walk polylines,
-                64-centre mixture); all 4,096 tiles of zoom 6; width 1 px.
+  c4 (default)  >= 2e8 star-polygon edges; 4,096 mixed requests per launch at
+                zooms 2-20, widths 1-5 px, against one launch per tile.
   c1            10,000 uniform points; all 256 tiles of zoom 4; radius 2 px.
+  c2            10,000,000 linestring segments (random-walk polylines,
+                64-centre mixture); all 4,096 tiles of zoom 6; width 1 px.
   c3            1e9 clustered points; 10,000 density-proportional tiles at
                 zooms 0-18, radius 1-3 px.
-  c4            >= 2e8 star-polygon edges; 4,096 mixed requests per launch at
-                zooms 2-20, widths 1-5 px.
+  c4fill        the c4 polygons filled (Algorithm 2) over the c4 requests.
   c5            serving: the c2 and c3 indexes resident; Poisson arrivals at
                 1k-50k requests/s over both, zooms 0-20, mixed styles;
                 continuous batching on two streams against one launch per
@@ -20,10 +21,12 @@ Workloads (--workload):
 Reported beside the batched figure: per-request latency p50/p99 inside a
 batch (device completion stamps), the same requests as one plain
 hv_render_batch call, and as one launch per request (p50/p99 of each
-launch); the index build time; the query kernels against the HBM roofline
-(algorithmic bytes per launch from the oracle's work counters, and HBM
-traffic from committed rocprofv3 counters while the query source is
-unchanged); and the CPU oracle timed on a bounded sample of the workload.
+launch); the index build time; the query kernel against its roofline
+(algorithmic bytes and flops per launch from the oracle's work counters,
+the bound being whichever takes longer at peak, and HBM traffic from
+committed rocprofv3 counters taken in the same launch shape while the query
+source is unchanged); and the CPU oracle timed on a bounded sample of the
+workload, on all host cores and on one thread.
 """
 from __future__ import annotations
 
@@ -45,7 +48,7 @@ METRIC = "256×256 tiles/sec at 1 GPU + p50/p99 tile latency; batched vs per-til
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 WORK_FILE = os.path.join(ROOT, "tests", "golden", "algorithmic_work.json")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_query_linestrings10M_z6.json")
+COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_query_*.json")
 QUERY_SOURCE = os.path.join(ROOT, "paper_2005_12489_amd", "csrc", "hv_query.hip")
 
 WORKLOADS = {
@@ -119,52 +122,163 @@ def source_hash() -> str:
     return hashlib.sha256(open(QUERY_SOURCE, "rb").read()).hexdigest()
 
 
-def cpu_baseline(objs, kind, tiles, r, seconds: float):
-    """The oracle (as it stands) on a bounded random sample of the requests.
+def launch_key(launch) -> dict:
+    """A launch shape with every field spelled out (None = the default)."""
+    fields = ("block", "cand_cap", "waves_per_wg", "grid_wgs", "region", "objs_per_lane", "cull_nodes")
+    return None if launch is None else {k: int(launch.get(k, 0) or 0) for k in fields}
 
-    For sets too large for the host oracle (above 5e7 objects) its index is
-    built over the objects that can reach the sampled tiles only."""
+
+def committed_traffic(workload: str, kernel: str, launch):
+    """HBM bytes per launch of the query kernel from committed rocprofv3
+    counters (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+    reads for a plain copy of known size), used only when they were taken on
+    this workload, with this kernel, in this exact launch shape and with the
+    query source as it is now."""
+    import glob
+    want = launch_key(launch)
+    for path in sorted(glob.glob(COUNTERS_GLOB)):
+        c = json.load(open(path))
+        for e in c.get("runs", [c]):
+            if (e.get("workload") == workload and e.get("kernel") == kernel and e.get("launch") == want
+                    and e.get("query_source_sha256") == source_hash()):
+                return e["hbm_bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
+
+
+def roofline_record(workload: str, launch, frontier_ms: float, query_ms: float):
+    """The query kernel against its roofline.  Algorithmic work per launch
+    comes from the oracle's counters (tests/golden/algorithmic_work.json):
+    bytes = masks + the objects unlit pixels need, flops = the exact
+    distance tests those pixels need plus one witness per lit pixel.  The
+    roofline time is max(bytes / 8 TB/s, flops / 78.6 TFLOP/s); the larger
+    term names the bound ("hbm" or "alu": FP64 vector arithmetic), and the
+    other side is reported beside it."""
+    work = json.load(open(WORK_FILE)).get(workload) if os.path.exists(WORK_FILE) else None
+    if not work:
+        return None
+    kname = query_kernel_name(launch)
+    sec = query_ms * 1e-3
+    gbs = work["alg_bytes"] / sec / 1e9
+    tfl = work["alg_flops"] / sec / 1e12
+    t_bytes = work["alg_bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_flops = work["alg_flops"] / (FP64_PEAK_TFLOPS * 1e12)
+    traffic, src = committed_traffic(workload, kname, launch)
+    rec = {"kernel": kname, "kernel_ms": query_ms, "frontier_kernel_ms": frontier_ms,
+           "alg_bytes_per_launch": work["alg_bytes"], "alg_flops_per_launch": work["alg_flops"],
+           "roofline_ms": max(t_bytes, t_flops) * 1e3, "traffic": traffic, "traffic_source": src,
+           "traffic_gbs": traffic / sec / 1e9 if traffic else None}
+    if t_flops > t_bytes:
+        rec.update({"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tfl / FP64_PEAK_TFLOPS, "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS})
+    else:
+        rec.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "fp64_tflops": tfl, "fp64_frac": tfl / FP64_PEAK_TFLOPS})
+    order = ("bound", "achieved", "peak", "unit", "frac", "traffic")
+    return {**{k: rec[k] for k in order}, **{k: v for k, v in rec.items() if k not in order}}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _near_first_vertex(objs, tiles, pick):
+    """Indices of the objects whose first vertex lies in a zoom-8 cell that a
+    picked tile covers, or in one of the cells around it (1.4 degrees).  Own
+    projection of the first vertex: this only chooses which objects the
+    timing sample's index holds."""
+    lon = objs[:, 0]
+    lat = np.clip(objs[:, 1], -85.0511287798066, 85.0511287798066)
+    cx = np.minimum(((lon + 180.0) / 360.0 * 256).astype(np.int32), 255)
+    cy = np.minimum(((0.5 - np.arctanh(np.sin(np.radians(lat))) / (2 * np.pi)) * 256).astype(np.int32), 255)
+    need = np.zeros((256, 256), dtype=bool)
+    for t in pick:
+        z, x, y = (int(v) for v in tiles[t])
+        if z >= 8:
+            x0 = x1 = x >> (z - 8)
+            y0 = y1 = y >> (z - 8)
+        else:
+            x0, x1 = x << (8 - z), ((x + 1) << (8 - z)) - 1
+            y0, y1 = y << (8 - z), ((y + 1) << (8 - z)) - 1
+        need[max(0, y0 - 1):min(255, y1 + 1) + 1, max(0, x0 - 1):min(255, x1 + 1) + 1] = True
+    return np.nonzero(need[cy, cx])[0]
+
+
+def cpu_baseline(objs, kind, tiles, r, seconds: float, zmin: int = 0):
+    """The oracle (as it stands) timed on a bounded sample of the requests,
+    on all host cores and on one thread, index build untimed.
+
+    Sets of up to 5e7 objects: the oracle indexes all of them and renders
+    requests drawn at random.  Larger sets: the sample is stratified by zoom,
+    the same number of requests at every zoom the workload draws (its zooms
+    are uniform, so the sample has the workload's zoom mix), and the oracle
+    indexes the objects whose first vertex lies within one zoom-8 cell of a
+    sampled tile.  zmin > 0 leaves out the zooms below it (tiles that hold
+    too much of a very large set for a host index built inside a bench)."""
     import oracle
-    order = np.random.default_rng(12345).permutation(len(tiles))
     threads = oracle.default_threads()
-    note = ""
-    if objs.shape[0] > 50_000_000:
-        # A host index over the whole set is out of reach here, so the sample
-        # is drawn from the requests at zoom >= 8 and the oracle indexes the
-        # objects whose first vertex lies within one zoom-8 cell (1.4 degrees)
-        # of one of them.
-        deep = order[tiles[order, 0] >= 8]
-        sample = deep[:64]
-        stage("oracle baseline: projecting the objects to pick the sample's")
-        X, Y = oracle.project(objs[:, :2])
-        cell = np.minimum((Y * 256).astype(np.int32), 255) * 256 + np.minimum((X * 256).astype(np.int32), 255)
-        del X, Y
-        need = set()
-        for t in sample:
-            z, x, y = (int(v) for v in tiles[t])
-            x0 = x >> (z - 8)
-            y0 = y >> (z - 8)
-            for cy in range(max(0, y0 - 1), min(255, y0 + 1) + 1):
-                for cx in range(max(0, x0 - 1), min(255, x0 + 1) + 1):
-                    need.add(cy * 256 + cx)
-        stage("oracle baseline: selecting")
-        objs = objs[np.isin(cell, np.fromiter(need, dtype=np.int32))]
-        order = sample
-        note = (f"; {len(sample)} requests drawn among those at zoom >= 8 only, and an index over the "
-                f"{objs.shape[0]} objects whose first vertex lies within one zoom-8 cell of them")
+    rng = np.random.default_rng(12345)
+    zs = np.unique(tiles[:, 0])
+    zs = zs[zs >= zmin]
+    whole = objs.shape[0] <= 50_000_000
+    if whole:
+        order = rng.permutation(len(tiles))
+        note = f"requests drawn at random (seed 12345) from the {len(tiles)}; index over all {objs.shape[0]} objects"
+    else:
+        per = 3
+        order = np.concatenate([rng.permutation(np.nonzero(tiles[:, 0] == z)[0])[:per] for z in zs])
+        order = order[rng.permutation(len(order))]
+        stage(f"oracle baseline: selecting the objects near {len(order)} sampled requests")
+        keep = _near_first_vertex(objs, tiles, order)
+        objs = objs[keep]
+        mix = "the workload's zoom mix" if zmin <= tiles[:, 0].min() else f"zooms below {zmin} left out"
+        note = (f"{per} requests per zoom (zooms {zs.min()}-{zs.max()}, seed 12345; {mix}); "
+                f"index over the {objs.shape[0]} objects whose first vertex lies within one zoom-8 cell of them")
     stage(f"oracle baseline: building the oracle index over {objs.shape[0]} objects")
     ix = oracle.OracleIndex(objs, kind)
-    stage("oracle baseline: rendering")
-    done, t0 = 0, time.perf_counter()
-    chunk = max(threads, 8)
-    while done < len(order) and time.perf_counter() - t0 < seconds:
-        sel = order[done:done + chunk]
-        ix.render(tiles[sel], r[sel], nthreads=threads, want_bit=False)
-        done += len(sel)
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "tiles/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} requests drawn at random (seed 12345) from the {len(tiles)}, "
-                      f"{dt:.1f} s of CPU work on {threads} threads; index build untimed{note}"}
+
+    def timed(nthreads, budget, chunk):
+        done, t0 = 0, time.perf_counter()
+        while done < len(order) and time.perf_counter() - t0 < budget:
+            sel = order[done:done + chunk]
+            ix.render(tiles[sel], r[sel], nthreads=nthreads, want_bit=False)
+            done += len(sel)
+        return done, time.perf_counter() - t0
+
+    stage(f"oracle baseline: rendering on {threads} threads")
+    n_all, t_all = timed(threads, seconds, max(threads, 8) if len(order) > 512 else len(order))
+    stage(f"oracle baseline: {n_all} requests in {t_all:.1f} s; one thread")
+    per_zoom = {}
+    if not whole or len(zs) > 1:
+        # one thread, request by request, so that the time per zoom is known
+        t1 = 0.0
+        n1 = 0
+        for t in order:
+            c0 = time.perf_counter()
+            ix.render(tiles[t:t + 1], r[t:t + 1], nthreads=1, want_bit=False)
+            dt = time.perf_counter() - c0
+            t1 += dt
+            n1 += 1
+            z = int(tiles[t, 0])
+            e = per_zoom.setdefault(str(z), [0, 0.0])
+            e[0] += 1
+            e[1] += dt
+            if t1 > seconds:
+                break
+        per_zoom = {z: {"requests": v[0], "ms_per_tile_1thread": v[1] / v[0] * 1e3} for z, v in per_zoom.items()}
+    else:
+        n1, t1 = timed(1, seconds / 2, 8)
+    return {"value": n_all / t_all, "unit": "tiles/s", "cores": threads, "kind": "oracle",
+            "value_1thread": n1 / t1, "cpu_model": cpu_model(),
+            "sample": f"{n_all} of the {len(order)} sampled requests on {threads} threads ({t_all:.1f} s) and "
+                      f"{n1} on one thread ({t1:.1f} s); {note}; index build untimed",
+            "per_zoom_1thread": per_zoom or None}
 
 
 def serve_bench(args, hv, torch):
@@ -334,7 +448,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--scale", type=float, default=1.0, help="object-count scale for c3 / c4")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -458,32 +572,13 @@ def main():
         lat = [a.elapsed_time(b) for a, b in pe]
         per_tile = {"tiles_per_s": m / (q1 - q0), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "launches": m}
 
-    roofline = None
-    work = json.load(open(WORK_FILE)).get(wl["name"]) if os.path.exists(WORK_FILE) else None
-    if work:
-        # every algorithmic byte (all masks, every object an unlit pixel needs)
-        # belongs to the query kernel; the frontier kernel only reads nodes
-        bytes_launch = work["alg_bytes"]
-        achieved = bytes_launch / (query_ms * 1e-3) / 1e9
-        kname = query_kernel_name(launch)
-        traffic = None
-        if os.path.exists(COUNTERS_FILE):
-            c = json.load(open(COUNTERS_FILE))
-            if (c.get("workload") == wl["name"] and c.get("query_source_sha256") == source_hash()
-                    and c.get("kernel") == kname):
-                traffic = c["hbm_bytes_per_launch"]
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "kernel": kname, "kernel_ms": query_ms, "frontier_kernel_ms": frontier_ms,
-                    "alg_bytes_per_launch": bytes_launch,
-                    "fp64_tflops": work["alg_flops"] / (query_ms * 1e-3) / 1e12,
-                    "fp64_frac": work["alg_flops"] / (query_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                    "traffic_gbs": traffic / (query_ms * 1e-3) / 1e9 if traffic else None}
+    roofline = roofline_record(wl["name"], launch, frontier_ms, query_ms)
 
     cpu = None
     if not args.no_cpu_baseline:
         stage("oracle baseline")
-        cpu = cpu_baseline(objs, wl["kind"], tiles, rr, args.cpu_seconds)
+        cpu = cpu_baseline(objs, wl["kind"], tiles, rr, args.cpu_seconds,
+                           zmin=6 if args.workload == "c3" else 0)
 
     hv.hv_free(h)
     rec = {

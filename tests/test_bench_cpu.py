@@ -29,3 +29,43 @@ def test_query_kernel_names():
     assert b.query_kernel_name({"region": 32, "objs_per_lane": 0}) == "k_query_region<32, 1>"
     assert b.query_kernel_name({"region": 0, "block": 8}) == "k_query<8>"
     assert b.query_kernel_name({"block": 0}) == "k_query<16>"
+
+
+def test_roofline_bound_is_the_slower_roof(tmp_path, monkeypatch):
+    """The larger of bytes / 8 TB/s and flops / 78.6 TFLOP/s names the bound;
+    the fraction is achieved over that roof's peak."""
+    import json
+    b = _bench_module()
+    work = {"w-bytes": {"alg_bytes": 8_000_000_000, "alg_flops": 1_000_000},
+            "w-flops": {"alg_bytes": 8_000_000, "alg_flops": 78_600_000_000}}
+    f = tmp_path / "work.json"
+    f.write_text(json.dumps(work))
+    monkeypatch.setattr(b, "WORK_FILE", str(f))
+    monkeypatch.setattr(b, "COUNTERS_GLOB", str(tmp_path / "none_*.json"))
+    r = b.roofline_record("w-bytes", None, 0.1, 2000.0)      # 8 GB in 2 s: 4 GB/s
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["achieved"] - 4.0) < 1e-9 and abs(r["frac"] - 4.0 / 8000.0) < 1e-12
+    assert abs(r["roofline_ms"] - 1.0) < 1e-12 and r["traffic"] is None
+    r = b.roofline_record("w-flops", None, 0.1, 1000.0)      # 78.6 GFLOP in 1 s
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert abs(r["achieved"] - 0.0786) < 1e-12 and abs(r["frac"] - 0.001) < 1e-12
+    assert list(r)[:6] == ["bound", "achieved", "peak", "unit", "frac", "traffic"]
+    assert b.roofline_record("absent", None, 0.1, 1.0) is None
+
+
+def test_counters_are_matched_on_the_full_launch(tmp_path, monkeypatch):
+    import json
+    b = _bench_module()
+    L = {"block": 0, "cand_cap": 128, "waves_per_wg": 1, "grid_wgs": 0, "region": 32, "objs_per_lane": 2,
+         "cull_nodes": 0}
+    run = {"workload": "w", "kernel": "k_query_region<32, 2>", "launch": L,
+           "query_source_sha256": b.source_hash(), "hbm_bytes_per_launch": 123.0}
+    (tmp_path / "counters_query_w.json").write_text(json.dumps({"runs": [run]}))
+    monkeypatch.setattr(b, "COUNTERS_GLOB", str(tmp_path / "counters_query_*.json"))
+    assert b.committed_traffic("w", "k_query_region<32, 2>", dict(L))[0] == 123.0
+    assert b.committed_traffic("w", "k_query_region<32, 2>", {**L, "cull_nodes": 32})[0] is None
+    assert b.committed_traffic("w", "k_query_region<32, 2>", None)[0] is None
+    assert b.committed_traffic("v", "k_query_region<32, 2>", dict(L))[0] is None
+    run["query_source_sha256"] = "0" * 64
+    (tmp_path / "counters_query_w.json").write_text(json.dumps(run))
+    assert b.committed_traffic("w", "k_query_region<32, 2>", dict(L))[0] is None
