@@ -433,6 +433,9 @@ class _Subset:
     def __init__(self, ex, ids):
         self.ex, self.ids = ex, ids
 
+    def request_bytes(self, rid):
+        return self.ex.request_bytes(int(self.ids[rid]))
+
     def idle_lane(self):
         return self.ex.idle_lane()
 

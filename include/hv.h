@@ -296,6 +296,25 @@ hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *
 int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
                    const hv_launch *launch);
 
+/* Device memory a request holds while it is in a batch (the task pool's
+ * admission unit, Sec. 4.2: the task pool and result pool live within a
+ * memory limit): its records in the batch workspace -- the request, its
+ * tile frontier of up to 256 nodes (the candidate buffer its regions start
+ * from), the frontier's size, level and region bits, its work-list entries,
+ * part counter and completion stamp -- plus its 8192-byte mask.  The value
+ * is the library's own and follows its workspace layout.  index, tile and
+ * style are validated as hv_render_batch validates a request (style may be
+ * NULL for a polygon index).  Returns the bytes (> 0), or HV_EINVAL. */
+int64_t hv_estimate_bytes(const hv_index *index, const hv_tile *tile, const hv_style *style);
+
+/* Device memory of a whole batch of n_requests requests over n_indexes
+ * distinct indexes: its workspace (header, index table, requests and
+ * per-request records, each array aligned to 256 bytes) plus the masks.  It
+ * is at most n_requests * hv_estimate_bytes(...) + 2304 + 80 * n_indexes
+ * bytes.  Returns the bytes, or HV_EINVAL for a negative count or more than
+ * 4096 indexes. */
+int64_t hv_estimate_batch_bytes(int64_t n_requests, int32_t n_indexes);
+
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Renders a
  * batch exactly as hv_render_batch does (same arguments, kernels and masks)

@@ -663,6 +663,29 @@ int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     return HV_OK;
 }
 
+int64_t hv_estimate_bytes(const hv_index *index, const hv_tile *tile, const hv_style *style) {
+    if (!index || !tile) return fail(HV_EINVAL, "index or tile is NULL");
+    int rc = validate_tiles(tile, 1);
+    if (rc) return rc;
+    if (index->kind != HV_POLYGONS && (rc = validate_style(style))) return rc;
+    // A request's records in a batch workspace (request, tile frontier, its
+    // size, level and region bits, list entries, part counter, completion
+    // stamp), taken from the layout itself: two batch sizes that are
+    // multiples of 256 leave no alignment padding between them.
+    const hv::Workspace a = hv::workspace_layout(256, 1), b = hv::workspace_layout(512, 1);
+    const int64_t per_request = (int64_t)(b.total - a.total) / 256;
+    t_err.clear();
+    return per_request + HV_MASK_BYTES;
+}
+
+int64_t hv_estimate_batch_bytes(int64_t n_requests, int32_t n_indexes) {
+    if (n_requests < 0 || n_indexes < 0 || n_indexes > 4096)
+        return fail(HV_EINVAL, "n_requests < 0 or n_indexes outside [0, 4096]");
+    const hv::Workspace w = hv::workspace_layout(n_requests, n_indexes);
+    t_err.clear();
+    return (int64_t)w.total + n_requests * (int64_t)HV_MASK_BYTES;
+}
+
 int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out) {
     if (!out || n <= 0 || !reqs) return fail(HV_EINVAL, "NULL argument or empty batch");
     for (int64_t k = 0; k < n; ++k)

@@ -45,7 +45,7 @@ SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free",
            "hv_set_stream", "hv_index_info", "hv_index_read", "hv_render_batch", "hv_batcher_create",
            "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch",
            "hv_time_kernels", "hv_render_batch_aa", "hv_polygon_index_build", "hv_render_fill",
-           "hv_render_batch_noalloc")
+           "hv_render_batch_noalloc", "hv_estimate_bytes", "hv_estimate_batch_bytes")
 
 # hv_request as a numpy record (32 bytes, the C layout)
 REQUEST_DTYPE = np.dtype([("index", np.uint64), ("z", np.int32), ("x", np.int32), ("y", np.int32),
@@ -105,6 +105,10 @@ lib.hv_index_read.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64
 
 lib.hv_render_batch.restype = ctypes.c_int
 lib.hv_render_batch.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
+lib.hv_estimate_bytes.restype = ctypes.c_int64
+lib.hv_estimate_bytes.argtypes = [_P, ctypes.POINTER(hv_tile), ctypes.POINTER(hv_style)]
+lib.hv_estimate_batch_bytes.restype = ctypes.c_int64
+lib.hv_estimate_batch_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
 lib.hv_render_batch_noalloc.restype = ctypes.c_int
 lib.hv_render_batch_noalloc.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch)]
 lib.hv_batcher_create.restype = _P
@@ -273,6 +277,19 @@ def hv_render_batch(reqs, out_masks, launch=None) -> None:
     _sync_stream()
     _check(lib.hv_render_batch(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_masks),
                                ctypes.byref(L) if L else None))
+
+
+def hv_estimate_bytes(index: int, tile, r_px: float | None) -> int:
+    """Device bytes one request of (index, tile (z, x, y), r) holds in a batch."""
+    z, x, y = (int(v) for v in tile[:3])
+    t = hv_tile(z, x, y, 0)
+    st = hv_style(float(r_px)) if r_px is not None else None
+    return _check(lib.hv_estimate_bytes(index, ctypes.byref(t), ctypes.byref(st) if st else None))
+
+
+def hv_estimate_batch_bytes(n_requests: int, n_indexes: int) -> int:
+    """Device bytes of a batch of n_requests requests over n_indexes indexes."""
+    return _check(lib.hv_estimate_batch_bytes(int(n_requests), int(n_indexes)))
 
 
 def hv_render_batch_noalloc(reqs, out_masks, launch=None) -> None:

@@ -7,9 +7,10 @@ Here the same roles map onto one GPU:
 
 * ``Scheduler`` -- the task pool.  Arrived requests wait in FIFO order and
   are admitted while in-flight slots and device memory allow; each admitted
-  request holds ``request_bytes`` of device memory (its tile frontier --
-  the candidate buffer of its pixel blocks -- its bookkeeping and its 8 KiB
-  mask) until its result is back on the host.
+  request holds the device bytes the library reports for it
+  (hv_estimate_bytes: its tile frontier -- the candidate buffer its regions
+  start from -- its bookkeeping and its 8 KiB mask) until its result is back
+  on the host.
 * ``GpuExecutor`` -- the engine.  One graph-captured ``hv_batcher`` per HIP
   stream; whenever a stream is idle, everything admitted so far is launched
   on it as one batch (continuous batching), so batches on different streams
@@ -127,49 +128,75 @@ class ResultCache:
             self.evicted += 1
 
 
-def workspace_bytes_per_request() -> int:
-    """Device workspace one request occupies in a batch: request record (24 B),
-    frontier (256 x 4 B), frontier size, level and region bits (16 B),
-    work-list and empty-list entries (2 x 4 B), completion counter (4 B) and
-    stamp (8 B)."""
-    return 24 + 256 * 4 + 16 + 4 + 4 + 4 + 8
+def request_bytes(index: int, tile, r_px: float) -> int:
+    """Device bytes one request holds while it is in a batch, as the library
+    itself counts them (hv_estimate_bytes: its records in the batch
+    workspace -- the tile frontier its regions start from among them -- and
+    its mask)."""
+    from . import hv
+    return hv.hv_estimate_bytes(int(index), tile, r_px)
 
 
 @dataclass
 class Scheduler:
-    """FIFO admission and batching; pure host logic with an injected clock."""
+    """FIFO admission and batching; pure host logic with an injected clock.
+
+    A queued request is admitted when an in-flight slot is free and its
+    device bytes fit in what is left of ``mem_budget``; admission stops at
+    the first request that does not fit (FIFO).  ``request_bytes`` gives a
+    request's bytes: a number for all of them, or a function of the request
+    id; None takes the executor's (``serve`` fills it in)."""
     max_batch: int = 4096                 # requests per launch
     max_inflight: int = 16384             # admitted and not yet complete
     mem_budget: int = 1 << 30             # device bytes for admitted requests
-    request_bytes: int = MASK_BYTES + workspace_bytes_per_request()
+    request_bytes: object = None
     queue: collections.deque = field(default_factory=collections.deque)
     inflight: int = 0
     mem_used: int = 0
     peak_mem: int = 0
     peak_inflight: int = 0
+    _held: dict = field(default_factory=dict)
+
+    def _bytes(self, rid: int) -> int:
+        rb = self.request_bytes
+        if rb is None:
+            raise ValueError("Scheduler.request_bytes is not set")
+        return int(rb(rid)) if callable(rb) else int(rb)
 
     def arrive(self, rid: int) -> None:
         self.queue.append(rid)
 
     def admissible(self) -> int:
-        """How many queued requests could be admitted now."""
-        by_slots = self.max_inflight - self.inflight
-        by_mem = (self.mem_budget - self.mem_used) // self.request_bytes
-        return max(0, min(len(self.queue), by_slots, by_mem, self.max_batch))
+        """How many queued requests (from the head) could be admitted now."""
+        room = min(len(self.queue), self.max_inflight - self.inflight, self.max_batch)
+        free = self.mem_budget - self.mem_used
+        k = 0
+        while k < room:
+            b = self._bytes(self.queue[k])
+            if b > free:
+                break
+            free -= b
+            k += 1
+        return max(0, k)
 
     def take_batch(self) -> list:
         """Admit and return the next batch (FIFO), or [] if nothing fits."""
         k = self.admissible()
         batch = [self.queue.popleft() for _ in range(k)]
+        for rid in batch:
+            b = self._bytes(rid)
+            self._held[rid] = b
+            self.mem_used += b
         self.inflight += k
-        self.mem_used += k * self.request_bytes
         self.peak_mem = max(self.peak_mem, self.mem_used)
         self.peak_inflight = max(self.peak_inflight, self.inflight)
         return batch
 
-    def complete(self, n: int) -> None:
-        self.inflight -= n
-        self.mem_used -= n * self.request_bytes
+    def complete(self, ids) -> None:
+        """Releases the slots and bytes of completed requests."""
+        for rid in ids:
+            self.mem_used -= self._held.pop(int(rid))
+        self.inflight -= len(ids)
         assert self.inflight >= 0 and self.mem_used >= 0
 
 
@@ -177,12 +204,26 @@ class GpuExecutor:
     """Batches on several HIP streams, each with its own graph-captured batcher."""
 
     def __init__(self, reqs: np.ndarray, streams: int = 2, max_batch: int = 4096, max_indexes: int = 8,
-                 max_levels: int = 10, launch=None, keep_masks: bool = False, return_masks: bool = False):
+                 max_levels: int = 10, launch=None, keep_masks: bool = False, return_masks: bool = False,
+                 mem_budget: int | None = None):
+        """reqs: the hv_request array of every request that may be served.
+        mem_budget: the device bytes the scheduler admits against; a lane
+        then holds no more requests than that budget admits at once."""
         import torch
 
         from . import hv
         self.hv, self.torch = hv, torch
         self.reqs = reqs
+        # the library's own count of the device bytes each request holds in a batch
+        self.bytes = np.array([hv.hv_estimate_bytes(int(q["index"]), (q["z"], q["x"], q["y"]), float(q["r_px"]))
+                               for q in reqs], dtype=np.int64)
+        if mem_budget is not None and len(reqs):
+            max_batch = max(1, min(max_batch, int(mem_budget // int(self.bytes.min()))))
+        self.max_batch = max_batch
+        # device memory the executor holds: per lane a batcher (two workspaces)
+        # and the masks of one batch
+        ws = hv.hv_estimate_batch_bytes(max_batch, max_indexes) - max_batch * MASK_BYTES
+        self.device_bytes = streams * (2 * ws + max_batch * MASK_BYTES)
         self.keep_masks = keep_masks
         self.return_masks = return_masks
         self.masks = np.zeros((len(reqs), MASK_BYTES), dtype=np.uint8) if keep_masks else None
@@ -197,6 +238,9 @@ class GpuExecutor:
                 "host": torch.empty((max_batch, MASK_BYTES), dtype=torch.uint8, pin_memory=True),
                 "event": torch.cuda.Event(),
             })
+
+    def request_bytes(self, rid: int) -> int:
+        return int(self.bytes[rid])
 
     def idle_lane(self):
         for k, ln in enumerate(self.lanes):
@@ -250,6 +294,8 @@ def serve(arrivals: np.ndarray, scheduler: Scheduler, executor, clock=time.perf_
     n = len(arrivals)
     if max_batch is not None:
         scheduler.max_batch = max_batch
+    if scheduler.request_bytes is None:
+        scheduler.request_bytes = executor.request_bytes
     keep = getattr(executor, "masks", None)
     keyed = requests is not None
     if keyed:
@@ -308,7 +354,7 @@ def serve(arrivals: np.ndarray, scheduler: Scheduler, executor, clock=time.perf_
             ids, t = res[0], res[1]
             rows = res[2] if len(res) > 2 else None
             done_at[ids] = t - t0
-            scheduler.complete(len(ids))
+            scheduler.complete(ids)
             finished += len(ids)
             if rows is not None and keep is not None:
                 keep[ids] = rows

@@ -90,5 +90,63 @@ def test_served_with_parse_rules_and_cache_equals_alone(hv, torch):
     ref = unpack_masks(alone.cpu().numpy())
     for k in range(n):
         assert np.array_equal(ref[k], served[k]), (k, int(st["status"][k]))
+    # and the oracle, on every request answered without a task of its own
+    # (empty tiles, pool hits, joined duplicates) and on a sample of the rest
+    status = st["status"]
+    keys = [(int(ds[i]), *map(int, arr["tiles"][i]), float(arr["r"][i])) for i in range(n)]
+    first = {}
+    for i, k in enumerate(keys):
+        first.setdefault(k, i)
+    repeat = np.array([first[k] != i for i, k in enumerate(keys)])
+    pick = np.nonzero((status == serve.EMPTY) | repeat)[0]
+    pick = np.concatenate([pick, np.nonzero((status == serve.TASK) & ~repeat)[0][:200]])
+    log(f"serve with parse rules and cache: oracle on {len(pick)} served masks "
+        f"({int((status == serve.EMPTY).sum())} empty, {int(repeat.sum())} repeats)")
+    objs = [(segs, oracle.SEGMENTS), (pts, oracle.POINTS), (small, oracle.POINTS)]
+    total_amb = 0
+    for d, (o, kind) in enumerate(objs):
+        sel = pick[ds[pick] == d]
+        if len(sel) == 0:
+            continue
+        tri = oracle.OracleIndex(o, kind).render(arr["tiles"][sel], arr["r"][sel])["tri"]
+        mism, amb, _ = parity(served[sel], tri)
+        total_amb += amb
+        assert mism == 0, d
+    assert total_amb <= 1e-6 * 65536 * len(pick) + 1
     for h in hs:
         hv.hv_free(h)
+
+
+def test_memory_budget_binds_before_slots(hv, torch):
+    """Admission by device memory: the budget admits 48 requests' bytes (the
+    library's own count per request) while thousands of slots are free, so
+    no more than 48 are ever in flight; every served mask still equals the
+    request rendered alone."""
+    from paper_2005_12489_amd import serve
+    segs = hvgen.gen_c2_segments(n_segments=300_000)
+    pts = hvgen.gen_c3_points(300_000)
+    h2, h3 = build(hv, torch, segs, hv.HV_SEGMENTS), build(hv, torch, pts, hv.HV_POINTS)
+    arr = hvgen.c5_arrivals(50000.0, c2_objects=segs, max_requests=2500, zmax=14)
+    reqs = hv.requests(np.where(arr["dataset"] == 0, h2, h3).astype(np.uint64), arr["tiles"], arr["r"])
+    per = serve.request_bytes(h2, arr["tiles"][0], 1.0)
+    budget = 48 * per
+    ex = serve.GpuExecutor(reqs, streams=2, max_batch=512, max_indexes=2, max_levels=12, keep_masks=True,
+                           mem_budget=budget)
+    assert ex.max_batch == 48
+    sch = serve.Scheduler(max_batch=512, max_inflight=16384, mem_budget=budget)
+    log(f"serve under a memory budget of {budget} bytes: {len(reqs)} requests at 50k req/s")
+    st = serve.serve(arr["t"], sch, ex)
+    ex.close()
+    log(f"peak in flight {sch.peak_inflight}, peak bytes {sch.peak_mem}, batches {st['batches']}, "
+        f"p99 {st['p99_ms']:.3f} ms")
+    assert sch.peak_mem <= budget and sch.peak_inflight <= 48 and sch.peak_inflight < sch.max_inflight
+    assert sch.peak_inflight == 48, "the load should fill the budget"
+    assert sch.inflight == 0 and sch.mem_used == 0
+    served = unpack_masks(ex.masks)
+    alone = torch.empty((1, 8192), dtype=torch.uint8, device="cuda")
+    for k in range(len(reqs)):
+        hv.hv_render_batch(reqs[k:k + 1], alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(unpack_masks(alone.cpu().numpy())[0], served[k]), k
+    hv.hv_free(h2)
+    hv.hv_free(h3)

@@ -19,12 +19,26 @@ class SimClock:
         self.t += max(dt, 0.0)
 
 
+def _lib_request_bytes():
+    """The library's own per-request device bytes (host call, no GPU)."""
+    from paper_2005_12489_amd import hv
+    h = hv.hv_index_build(None, hv.HV_SEGMENTS, 0)
+    try:
+        return serve_mod.request_bytes(h, (5, 3, 4), 1.0)
+    finally:
+        hv.hv_free(h)
+
+
 class FakeExecutor:
-    def __init__(self, clock, lanes=2, a=200e-6, b=2e-6, mask_of=None):
+    def __init__(self, clock, lanes=2, a=200e-6, b=2e-6, mask_of=None, per=None):
         self.clock, self.a, self.b = clock, a, b
+        self.per = per if per is not None else _lib_request_bytes()
         self.busy = [None] * lanes
         self.launched = []
         self.mask_of = mask_of
+
+    def request_bytes(self, rid):
+        return self.per
 
     def idle_lane(self):
         for k, x in enumerate(self.busy):
@@ -68,7 +82,7 @@ def test_every_request_served_once_in_fifo_batches():
 
 
 def test_batch_size_slots_and_memory_limits_hold():
-    per = serve_mod.Scheduler().request_bytes
+    per = _lib_request_bytes()
     st, ex, sch, _ = _run(200000.0, 6000, max_batch=300, mem_budget=700 * per, max_inflight=10000)
     assert max(len(b) for b in ex.launched) <= 300
     assert sch.peak_mem <= 700 * per
@@ -189,3 +203,49 @@ def test_expired_results_make_new_tasks():
                          parser=serve_mod.RequestParser([(0.0, 0.0, 1.0, 1.0)]), cache=cache)
     # 20 keys over 0.6 s with a 50 ms window: each key is rendered several times
     assert 20 < st["tasks"] < n and st["cache_hits"] > 0
+
+
+def test_request_bytes_follow_the_workspace_layout():
+    """hv_estimate_bytes is the mask plus the per-request growth of a batch's
+    workspace, and a batch never holds more than n requests' bytes plus the
+    stated fixed part."""
+    from paper_2005_12489_amd import hv
+    per = _lib_request_bytes()
+    assert per > hv.HV_MASK_BYTES + 256 * 4            # the mask and a 256-node frontier at least
+    for n in (256, 1024, 4096):
+        grow = hv.hv_estimate_batch_bytes(n + 256, 3) - hv.hv_estimate_batch_bytes(n, 3)
+        assert grow == 256 * per, (n, grow, per)
+    rng = np.random.default_rng(3)
+    for n, k in zip(rng.integers(0, 100_000, 50), rng.integers(1, 40, 50)):
+        b = hv.hv_estimate_batch_bytes(int(n), int(k))
+        assert n * per <= b <= n * per + 2304 + 80 * k, (n, k, b)
+    h = hv.hv_index_build(None, hv.HV_POINTS, 0)
+    try:
+        for tile, r in (((23, 0, 0), 1.0), ((3, 8, 0), 1.0), ((3, 1, 1), 0.0), ((3, 1, 1), 65.0)):
+            with pytest.raises(hv.HvError):
+                hv.hv_estimate_bytes(h, tile, r)
+    finally:
+        hv.hv_free(h)
+    with pytest.raises(hv.HvError):
+        hv.hv_estimate_batch_bytes(-1, 1)
+
+
+def test_memory_budget_binds_before_slots():
+    """With room for 40 requests' bytes and thousands of slots, no more than
+    40 requests are ever in flight; a request that needs more bytes than the
+    head room waits (FIFO), and bytes are released as requests complete."""
+    per = _lib_request_bytes()
+    st, ex, sch, _ = _run(500000.0, 4000, max_batch=4096, mem_budget=40 * per, max_inflight=16384)
+    assert sch.peak_inflight == 40 and sch.peak_mem == 40 * per
+    assert max(len(b) for b in ex.launched) <= 40
+    assert sch.inflight == 0 and sch.mem_used == 0 and np.all(np.isfinite(st["latency_s"]))
+    # bytes that differ per request: admission stops at the first that does not fit
+    sch = serve_mod.Scheduler(max_batch=100, max_inflight=100, mem_budget=1000,
+                              request_bytes=lambda rid: 300 if rid % 2 else 100)
+    for rid in range(10):
+        sch.arrive(rid)
+    assert sch.take_batch() == [0, 1, 2, 3, 4]         # 100 + 300 + 100 + 300 + 100 = 900
+    assert sch.take_batch() == []                      # request 5 needs 300, 100 are left
+    sch.complete([1])                                  # frees 300
+    assert sch.take_batch() == [5, 6]                  # 300 + 100 of the 400 now free
+    assert sch.mem_used == 1000 and sch.inflight == 6
