@@ -235,7 +235,9 @@ void hv_batcher_free(hv_batcher *b);
  * query kernels between HIP events, the fastest of the repeats).  Each shape
  * runs first on 16, then 128 evenly spread requests of the sample, then on
  * all of it, and is dropped once a part takes more than four times the
- * best time seen on that part.  The result is also cached under the
+ * best time seen on that part; on the whole sample a shape replaces the one
+ * chosen so far only if it is at least 3% faster (the candidates start with
+ * the default shapes).  The result is also cached under the
  * sample's class -- dominant kind, zoom band (z / 4), radius band (r <= 1,
  * <= 2, <= 4, > 4) and size band (n < 1024, < 4096, larger) -- which
  * hv_render_batch with launch == NULL then uses for batches of that class.  scratch_masks:

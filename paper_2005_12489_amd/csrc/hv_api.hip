@@ -742,6 +742,8 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
         return hip_status(e, "hv_autotune");
     }
     double stage_best[kStages] = {1e300, 1e300, 1e300};
+    constexpr double kMargin = 0.03;
+    double chosen_ms = 1e300;
     int best_k = -1;
     for (int k = 0; k < (int)(sizeof(cands) / sizeof(cands[0])) && rc == HV_OK && e == hipSuccess; ++k) {
         hv::LaunchShape shape;
@@ -766,10 +768,14 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
             }
             if (rc || e != hipSuccess) break;
             if (ms_min > kDrop * stage_best[st]) break;
-            if (ms_min < stage_best[st]) {
-                stage_best[st] = ms_min;
-                if (st == kStages - 1) best_k = k;
+            // on the whole sample a later candidate must beat the chosen one
+            // by kMargin, so that shapes within noise of each other do not
+            // trade places from run to run (the default shapes come first)
+            if (st == kStages - 1 && (best_k < 0 || ms_min < (1.0 - kMargin) * chosen_ms)) {
+                best_k = k;
+                chosen_ms = ms_min;
             }
+            if (ms_min < stage_best[st]) stage_best[st] = ms_min;
         }
     }
     for (int k = 0; k < 3; ++k) (void)hipEventDestroy(m[k]);
@@ -777,7 +783,7 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     if (e != hipSuccess) return hip_status(e, "hv_autotune");
     if (best_k < 0) return fail(HV_EINVAL, "no candidate shape fits this batch");
     *best = cands[best_k];
-    if (best_ms) *best_ms = stage_best[kStages - 1];
+    if (best_ms) *best_ms = chosen_ms;
     const TuneKey key = batch_key(sample, n);
     std::lock_guard<std::mutex> g(g_tune_mu);
     bool found = false;

@@ -41,6 +41,7 @@ namespace {
 constexpr uint32_t kBigFlag = 0x80000000u;  // staged object tested pixel-parallel
 constexpr int kSmallArea = 48;              // largest pixel range tested object-parallel
 constexpr double kRangeEps = 1e-7;          // px, widens every pixel range
+constexpr double kAcceptMargin = 1e-3;      // px: accepts in FP32 use the radius r - kAcceptMargin
 constexpr int kCandBytes = 16 + 16 + 8 + 4; // staged object: a, d, 1/|d|^2, range
 
 __device__ inline uint32_t lanes_below(uint64_t m) {
@@ -497,13 +498,21 @@ __global__ __launch_bounds__(256) void k_query(DevBatch B, int cap, int max_leve
 // lanes, whatever the objects' sizes: each cell tests at most 8 pixels
 // with the exact FP64 distance and sets the lit ones with one LDS OR.
 
-__host__ __device__ inline int region_stack_words(int levels, int threads) {
-    return kFrontier + threads * (levels > 0 ? levels : 1);
+// Most children an inner traversal step of a region tests (16 popped nodes).
+constexpr int kInnerWidth = 256;
+
+// A traversal step pops nodes of one level -- the lowest on the stack -- and
+// pushes at most min(threads * per_lane, kInnerWidth) of their children
+// (per_lane children tested by each thread), so every level below the
+// frontier holds at most that many entries at a time.
+__host__ __device__ inline int region_stack_words(int levels, int threads, int per_lane = 1) {
+    const int width = threads * per_lane < kInnerWidth ? threads * per_lane : kInnerWidth;
+    return kFrontier + width * (levels > 0 ? levels : 1);
 }
 
 // stack | queued objects (SoA) | cell prefix sums | mask rows | control | scan scratch
-__host__ __device__ inline size_t region_lds_bytes(int cap, int levels, int threads, int rs) {
-    return align16((size_t)region_stack_words(levels, threads) * 4) + align16((size_t)cap * kCandBytes) +
+__host__ __device__ inline size_t region_lds_bytes(int cap, int levels, int threads, int rs, int opl) {
+    return align16((size_t)region_stack_words(levels, threads, opl) * 4) + align16((size_t)cap * kCandBytes) +
            align16((size_t)(cap + 1) * 4) + align16((size_t)rs * (rs / 32) * 4) + 16 + 64;
 }
 
@@ -744,21 +753,41 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         }
         bool accepted = false;
         const int lvl = (int)(stk[sp - 1] >> kLevelShift);
-        // an inner step tests one child per thread; a leaf step OPL objects per thread
-        const int per_step = lvl > 0 ? nthr / kFan : nthr * OPL / kLeaf;
+        // a step tests OPL objects per thread at a leaf level, and up to OPL
+        // children per thread, kInnerWidth in all, at an inner one: 16 per
+        // popped node either way
+        const int per_step = (lvl > 0 ? min(nthr * OPL, kInnerWidth) : nthr * OPL) / kFan;
         const bool top = tid < per_step && tid < sp && (int)(stk[sp - 1 - tid] >> kLevelShift) == lvl;
         const int npop = __syncthreads_count(top);
         if (lvl > 0) {
-            const int j = tid >> 4, c = tid & 15;  // popped node, child of it
-            const uint32_t node = j < npop ? (stk[sp - 1 - j] & kIdxMask) : 0u;
+            const int cl = lvl - 1;
+            const int64_t ccount = ix.meta[kMaxLevels + cl], coff = ix.meta[cl];
+            // issue all OPL child-box loads first so that they are in flight together
+            double4 nbk[OPL];
+            uint32_t childk[OPL];
+            bool havek[OPL];
+#pragma unroll
+            for (int k = 0; k < OPL; ++k) {
+                const int q = k * nthr + tid, j = q >> 4, c = q & 15;  // popped node, child of it
+                havek[k] = false;
+                childk[k] = 0;
+                nbk[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+                if (j < npop) {
+                    const int64_t child = (int64_t)(stk[sp - 1 - j] & kIdxMask) * kFan + c;
+                    if (child < ccount) {
+                        havek[k] = true;
+                        childk[k] = (uint32_t)child;
+                        nbk[k] = ix.nodes[coff + child];
+                    }
+                }
+            }
             if (tid == 0) ctl[0] = sp - npop;
             __syncthreads();
-            const int cl = lvl - 1;
-            const int64_t child = (int64_t)node * kFan + c;
-            bool push = false;
-            if (j < npop && child < ix.meta[kMaxLevels + cl]) {
-                const double4 nb = ix.nodes[ix.meta[cl] + child];
-                if (meets(nb, qx0, qx1, qy0, qy1)) {
+#pragma unroll
+            for (int k = 0; k < OPL; ++k) {
+                const double4 nb = nbk[k];
+                bool push = false;
+                if (havek[k] && meets(nb, qx0, qx1, qy0, qy1)) {
                     const double bx0 = nb.x * S - ox, bx1 = nb.z * S - ox;
                     const double by0 = nb.y * S - oy, by1 = nb.w * S - oy;
                     int ilo, ihi, jlo, jhi;
@@ -766,26 +795,54 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     const double bw = bx1 - bx0, bh = by1 - by0;
                     const double diag2 = bw * bw + bh * bh;
                     const bool small = racc > 0.0 && bw <= 2.0 * racc && bh <= 2.0 * racc;
+                    // a child whose pixel range is all lit can add nothing:
+                    // neither accepts nor objects
+                    if (push && range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
                     if (push && small) {
                         // Edge accept.  A node box is the exact bounding box of
                         // its objects' coordinates (points, segment endpoints),
-                        // so each of its four edges holds a point of some object.
-                        // A pixel centre within racc of both ends of one edge is
-                        // within racc of that point, hence lit, without looking
-                        // at the objects.
-                        for (int jj = jlo; jj <= jhi; ++jj) {
-                            const double cy = j0 + (double)jj + 0.5;
-                            const double ey0 = fabs(cy - by0), ey1 = fabs(cy - by1);
-                            const double dyn = fmin(ey0, ey1), dyf = fmax(ey0, ey1);
-                            if (dyn * dyn > racc2) continue;
-                            uint64_t bits = 0;
-                            for (int ii = ilo; ii <= ihi; ++ii) {
-                                const double cx = i0 + (double)ii + 0.5;
-                                const double ex0 = fabs(cx - bx0), ex1 = fabs(cx - bx1);
-                                const double dxn = fmin(ex0, ex1), dxf = fmax(ex0, ex1);
-                                // nearer vertical edge, or nearer horizontal edge
-                                if (dxn * dxn + dyf * dyf <= racc2 || dxf * dxf + dyn * dyn <= racc2)
-                                    bits |= 1ull << ii;
+                        // so each of its four sides holds a point of some object.
+                        // A pixel centre within ra of both ends of one side is
+                        // within ra of that point, hence lit, without looking
+                        // at the objects.  Per pixel row at height cy, with dyn
+                        // and dyf the distances to the nearer and farther
+                        // horizontal side, that holds for the centres cx with
+                        //   |cx - bx0| <= a or |cx - bx1| <= a,  a = sqrt(ra^2 - dyf^2)
+                        //     (both ends of the vertical side at bx0 or bx1), or
+                        //   bx1 - b <= cx <= bx0 + b,            b = sqrt(ra^2 - dyn^2)
+                        //     (both ends of the nearer horizontal side),
+                        // so the row's accepted pixels are at most three runs.
+                        // The test runs in FP32 with ra = r - 1e-3 px.  Tile-local
+                        // coordinates stay below a few hundred px, where one FP32
+                        // rounding is at most 3e-5 px, so the squared distance a
+                        // claimed centre is known to have is off by less than
+                        // 2 r 1e-4 + r^2 3e-7 px^2 (the runs are shrunk by 1e-4
+                        // px for their own rounding): under a tenth of the room
+                        // r^2 - ra^2 = 2 r 1e-3 - 1e-6 for every r in (1e-3, 64].
+                        // No accept claims a centre beyond r; pixels near an
+                        // accept's edge fall to the exact FP64 test.
+                        const float ra = (float)(r - kAcceptMargin);
+                        const float ra2 = ra * ra;
+                        const float fx0 = (float)bx0, fx1 = (float)bx1, fy0 = (float)by0, fy1 = (float)by1;
+                        const float fc0 = (float)(i0 + 0.5);  // centre of region column 0 (exact)
+                        auto run = [&](float lo, float hi) -> uint64_t {
+                            const int a0 = max((int)ceilf(lo - fc0 + 1e-4f), ilo);
+                            const int a1 = min((int)floorf(hi - fc0 - 1e-4f), ihi);
+                            if (a0 > a1) return 0ull;
+                            return (a1 - a0 == 63 ? ~0ull : ((1ull << (a1 - a0 + 1)) - 1ull)) << a0;
+                        };
+                        for (int jj = jlo; jj <= jhi && ra > 0.0f; ++jj) {
+                            const float cy = (float)(j0 + (double)jj + 0.5);  // exact
+                            const float ey0 = fabsf(cy - fy0), ey1 = fabsf(cy - fy1);
+                            const float dyn = fminf(ey0, ey1), dyf = fmaxf(ey0, ey1);
+                            const float rn = ra2 - dyn * dyn;
+                            if (rn < 0.0f) continue;
+                            const float b = __builtin_amdgcn_sqrtf(rn);
+                            uint64_t bits = run(fx1 - b, fx0 + b);
+                            const float rf = ra2 - dyf * dyf;
+                            if (rf >= 0.0f) {
+                                const float a = __builtin_amdgcn_sqrtf(rf);
+                                bits |= run(fx0 - a, fx0 + a) | run(fx1 - a, fx1 + a);
                             }
 #pragma unroll
                             for (int wd = 0; wd < W; ++wd) {
@@ -796,8 +853,8 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                                 }
                             }
                         }
+                        if (range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
                     }
-                    if (push && range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
                     // The accept pass stops at leaves and at nodes whose diagonal
                     // is at most 1.5 racc.  A box's edge accepts light every pixel
                     // centre inside it once its diagonal is at most 2 racc (the
@@ -811,9 +868,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     if (accept_pass && push && (diag2 <= 2.25 * racc2 || cl == 0 || diag2 > ldexp(16.0 * racc2, 4 * cl)))
                         push = false;
                 }
+                const int pos = wave_alloc(&ctl[0], __ballot(push), lane);
+                if (push) stk[pos] = ((uint32_t)cl << kLevelShift) | childk[k];
             }
-            const int pos = wave_alloc(&ctl[0], __ballot(push), lane);
-            if (push) stk[pos] = ((uint32_t)cl << kLevelShift) | (uint32_t)child;
         } else {
             // issue all OPL loads first so that they are in flight together
             double4 ob[OPL];
@@ -898,13 +955,13 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
 }
 
 template <int RS, int OPL>
-__global__ __launch_bounds__(256) void k_query_region(DevBatch B, int cap, int max_levels) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_query_region(DevBatch B, int cap, int max_levels) {
     extern __shared__ double4 smem[];
     constexpr int RPT = (256 / RS) * (256 / RS);
     unsigned char *base = reinterpret_cast<unsigned char *>(smem);
     RegionLds L;
     L.stk = reinterpret_cast<uint32_t *>(base);
-    unsigned char *cb = base + align16((size_t)region_stack_words(max_levels, blockDim.x) * 4);
+    unsigned char *cb = base + align16((size_t)region_stack_words(max_levels, blockDim.x, OPL) * 4);
     L.ca = reinterpret_cast<double2 *>(cb);
     L.cd = L.ca + cap;
     L.ci = reinterpret_cast<double *>(L.cd + cap);
@@ -1276,7 +1333,7 @@ struct GridKey {
 
 size_t query_lds_bytes(const LaunchShape &s, int max_levels) {
     if (s.fill) return fill_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region);
-    if (s.region) return region_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region);
+    if (s.region) return region_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region, s.opl);
     return (size_t)s.waves * wave_lds_bytes(s.cand_cap, max_levels, s.block);
 }
 
