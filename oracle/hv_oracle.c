@@ -365,7 +365,7 @@ static int render_tile(const or_index *ix, int z, int64_t tx, int64_t ty, double
             if (dist) dist[p] = D;
             lit += b;
             amb += (t == 2);
-            if (!b) {
+            if (!b && npix > 0) {
                 nbox_unlit += npix;
                 if (grow(&sc->tile_ids, &sc->tile_cap, sc->tile_n + npix)) return -1;
                 memcpy(sc->tile_ids + sc->tile_n, sc->pix_ids, (size_t)npix * sizeof(int64_t));

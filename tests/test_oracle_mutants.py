@@ -50,11 +50,11 @@ MUTANTS = [
     # work counters (the roofline's algorithmic bytes and flops)
     ("cnt-widened-box", "if (box_meets(&b, &qr)) {", "if (box_meets(&b, &q)) {"),
     ("cnt-duplicates", "uniq += sc->tile_ids[q] != sc->tile_ids[q - 1];", "uniq += 1;"),
-    ("cnt-lit-pixels-too", "if (!b) {\n                nbox_unlit", "if (1) {\n                nbox_unlit"),
+    ("cnt-lit-pixels-too", "if (!b && npix > 0) {", "if (npix > 0) {"),
     ("cnt-lit-certain-only", "lit += b;", "lit += (t == 1);"),
     ("cnt-box-half-height", "obox qr = { (cx - r) / S, (cy - r) / S, (cx + r) / S, (cy + r) / S };",
      "obox qr = { (cx - r) / S, (cy - r) / S, (cx + r) / S, cy / S };"),
-    ("cnt-unlit-ambiguous-only", "if (!b) {\n                nbox_unlit", "if (t == 0) {\n                nbox_unlit"),
+    ("cnt-unlit-ambiguous-only", "if (!b && npix > 0) {", "if (t == 0 && npix > 0) {"),
 ]
 
 
