@@ -122,8 +122,8 @@ int hv_set_stream(void *hip_stream);
  * n < 1024, 2 for n < 4096 and 1 beyond (in a small batch the heaviest
  * regions set the time and more waves shorten them; a large one fills the
  * GPU with single-wave groups), cand_cap 128 * waves_per_wg and cull_nodes
- * 256.  For anti-aliased output n counts the 4 children of each request;
- * filling has its own default (hv_render_fill).  In a given shape, zero
+ * 256.  Anti-aliased output takes the same default; filling has its own
+ * (hv_render_fill).  In a given shape, zero
  * fields take block 16, waves_per_wg 2 (1 in region mode), objs_per_lane
  * 1, cand_cap 64 * waves_per_wg * objs_per_lane in region mode (64
  * otherwise), cull_nodes 256 and a grid that fills the GPU; region = 0
@@ -253,17 +253,18 @@ int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
  * -- that lie within r of some object of the request's index, each
  * sub-sample measured against its own nearest object (Algorithm 1 as
  * printed measures all four against the object nearest the centre, which
- * can count fewer).  The sub-samples of tile (z, x, y) are the pixel centres
- * of its four children at zoom z + 1, where the radius is 2r, so the library
- * renders those binary masks with the kernels of hv_render_batch into
- * stream-ordered scratch (4 x 8192 bytes per request, freed in stream order)
- * and sums each pixel's 2 x 2 bits.
- * reqs: host array as for hv_render_batch, with z <= HV_MAX_ZOOM - 1.
+ * can count fewer).  One pass of the region kernel, with four sub-sample
+ * masks per region: it culls with the samples' reach (r + 1/4 px per axis),
+ * lights whole pixels whose centre lies within r - sqrt(2)/4 px of an object
+ * (Algorithm 1's R1) without reading objects, and tests the four sub-samples
+ * of every other pixel in reach exactly (FP64, inclusive).
+ * reqs: host array as for hv_render_batch (0 <= z <= HV_MAX_ZOOM).
  * out_values: device, n * HV_AA_BYTES bytes, 16-byte aligned; the value of
  * pixel (i, j) of request k is at k * HV_AA_BYTES + j * 256 + i.
- * launch: the query shape (NULL = the default shape).  Asynchronous on the
- * calling thread's stream.  Errors as hv_render_batch, plus HV_EINVAL for
- * z = HV_MAX_ZOOM; nothing is launched on error. */
+ * launch: the query shape (NULL = the default shape for n requests; a shape
+ * with region = 0 runs with region 32, the one-pass form needing region
+ * mode).  Asynchronous on the calling thread's stream.  Errors as
+ * hv_render_batch; nothing is launched on error. */
 int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch);
 
 /* Polygon index for filling (Sec. 3.1, the multi-level index for polygons:

@@ -587,40 +587,25 @@ int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, c
     BatchPlan p;
     int rc = plan_batch(reqs, n, &p);
     if (rc) return rc;
-    for (int64_t k = 0; k < n; ++k)
-        if (reqs[k].z >= HV_MAX_ZOOM)
-            return fail(HV_EINVAL, "request " + std::to_string(k) + ": anti-aliased output needs z <= " +
-                                       std::to_string(HV_MAX_ZOOM - 1));
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, p.max_levels, &shape, 4 * n))) return rc;
+    if ((rc = resolve_shape(launch, p.max_levels, &shape, n))) return rc;
+    // one pass in region mode: four sub-sample masks per region
+    if (shape.region == 0) {
+        shape.region = 32;
+        if (!launch || !launch->cand_cap) shape.cand_cap = 64 * shape.waves * shape.opl;
+        if (shape.cand_cap < 64 * shape.waves * shape.opl) shape.cand_cap = 64 * shape.waves * shape.opl;
+    }
+    shape.aa = 1;
+    if (hv::query_lds_bytes(shape, p.max_levels) > 65536)
+        return fail(HV_EINVAL, "launch shape needs more than 64 KiB of LDS per workgroup");
     if (n == 0) {
         t_err.clear();
         return HV_OK;
     }
     if ((rc = validate_out(out_values))) return rc;
-    // the four children of each tile one zoom deeper, at twice the radius
-    std::vector<hv::DevReq> kids((size_t)(4 * n));
-    for (int64_t k = 0; k < n; ++k) {
-        const hv::DevReq &q = p.reqs[(size_t)k];
-        for (int c = 0; c < 4; ++c) {
-            hv::DevReq &d = kids[(size_t)(4 * k + c)];
-            d.z = q.z + 1;
-            d.x = 2 * q.x + (c & 1);
-            d.y = 2 * q.y + (c >> 1);
-            d.index = q.index;
-            d.r = 2.0 * q.r;
-        }
-    }
-    uint8_t *child = nullptr;
-    hipError_t e = hipMallocAsync((void **)&child, (size_t)(4 * n) * HV_MASK_BYTES, t_stream);
-    if (e != hipSuccess) return hip_status(e, "hv_render_batch_aa");
-    rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, kids.data(), 4 * n, child, shape,
+    rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_values, shape,
                    "hv_render_batch_aa");
-    if (rc == HV_OK) e = hv::launch_aa_reduce(child, n, out_values, t_stream);
-    const hipError_t ef = hipFreeAsync(child, t_stream);
     if (rc) return rc;
-    if (e != hipSuccess) return hip_status(e, "hv_render_batch_aa");
-    if (ef != hipSuccess) return hip_status(ef, "hv_render_batch_aa");
     t_err.clear();
     return HV_OK;
 }

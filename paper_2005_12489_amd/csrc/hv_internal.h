@@ -96,6 +96,7 @@ struct LaunchShape {
     int region;       // 0: one wave per block; 32 or 64: one workgroup per region of that side
     int opl;          // region mode: objects loaded per lane at a leaf step (1, 2 or 4)
     int fill = 0;     // 1: polygon filling (region mode) instead of the distance masks
+    int aa = 0;       // 1: anti-aliased values 0-4 (region mode, HV_AA_BYTES per request)
     int cull = kFrontier;  // frontier cap of the per-tile pass (cull depth)
 };
 
@@ -106,7 +107,7 @@ size_t query_lds_bytes(const LaunchShape &s, int max_levels);
 // so that a captured graph's kernel arguments never change.
 struct BatchHeader {
     int64_t n_req;      // live requests
-    uint8_t *out;       // masks: request k at out + k * 8192
+    uint8_t *out;       // request k at out + k * 8192 (anti-aliased values: k * 65536)
     int32_t counter;    // tiles appended to the compacted list (0 when staged)
     int32_t ecounter;   // tiles with no data within r, listed for zero-filling (0 when staged)
     uint64_t t_start;   // wall clock when the batch started on the device
@@ -148,10 +149,6 @@ DevBatch device_batch(const Workspace &w, unsigned char *dws);
 hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,
                         hipStream_t stream, hipEvent_t *marks = nullptr);
 
-// Sums the 2 x 2 sub-sample bits of each pixel from four child masks per
-// request (one zoom deeper, child 2 * dy + dx) into n anti-aliased tiles of
-// HV_AA_BYTES at `out` (device), on `stream`.
-hipError_t launch_aa_reduce(const uint8_t *child_masks, int64_t n, uint8_t *out, hipStream_t stream);
 
 // Workgroups that fill the current device for a shape (occupancy x CUs).
 int persistent_grid(const LaunchShape &s, int max_levels);

@@ -97,7 +97,9 @@ __device__ inline uint64_t wave_or64(uint64_t v) {
 // frontier records the regions its nodes can reach; 0 marks every part.
 // cull (1..kFrontier): the cull depth -- the walk goes one level deeper only
 // while that level holds at most cull nodes meeting the tile.
-__global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs, int cull) {
+// grow (px) widens the tile's box beyond r on every side: 1/4 for
+// anti-aliased output, whose sub-samples lie 1/4 px from the pixel centres.
+__global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs, int cull, double grow) {
     __shared__ uint32_t buf[4][2][kFrontier];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps per-tile values scalar
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs, int c
     const DevIndex ix = B.ixs[rq.index];
     const double iS = ldexp(1.0, -8 - rq.z), S = ldexp(256.0, rq.z);
     const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
-    const double m = rq.r + kCullPad;
+    const double m = rq.r + grow + kCullPad;
     const double qx0 = (ox + (0.5 - m)) * iS, qx1 = (ox + (255.5 + m)) * iS;
     const double qy0 = (oy + (0.5 - m)) * iS, qy1 = (oy + (255.5 + m)) * iS;
     uint32_t *cur = buf[wv][0], *nxt = buf[wv][1];
@@ -171,12 +173,12 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs, int c
 
 // Writes the zero masks of the requests whose tile has no data within r
 // (listed by the tile-frontier kernel); workgroups take them in turn.
-__device__ inline void zero_empty_tiles(const DevBatch &B, uint8_t *out) {
+__device__ inline void zero_empty_tiles(const DevBatch &B, uint8_t *out, int tile_bytes = HV_MASK_BYTES) {
     const int ne = B.hdr->ecounter;
     for (int e = blockIdx.x; e < ne; e += gridDim.x) {
         const int64_t t = B.elist[e];
-        uint4 *m4 = reinterpret_cast<uint4 *>(out + t * (int64_t)HV_MASK_BYTES);
-        for (int k = threadIdx.x; k < HV_MASK_BYTES / 16; k += blockDim.x) m4[k] = make_uint4(0, 0, 0, 0);
+        uint4 *m4 = reinterpret_cast<uint4 *>(out + t * (int64_t)tile_bytes);
+        for (int k = threadIdx.x; k < tile_bytes / 16; k += blockDim.x) m4[k] = make_uint4(0, 0, 0, 0);
         __syncthreads();
         if (threadIdx.x == 0) B.ts[t] = wall_clock64();
     }
@@ -510,10 +512,11 @@ __host__ __device__ inline int region_stack_words(int levels, int threads, int p
     return kFrontier + width * (levels > 0 ? levels : 1);
 }
 
-// stack | queued objects (SoA) | cell prefix sums | mask rows | control | scan scratch
-__host__ __device__ inline size_t region_lds_bytes(int cap, int levels, int threads, int rs, int opl) {
+// stack | queued objects (SoA) | cell prefix sums | mask rows (four sets for
+// anti-aliased output, one per sub-sample) | control | scan scratch
+__host__ __device__ inline size_t region_lds_bytes(int cap, int levels, int threads, int rs, int opl, int aa = 0) {
     return align16((size_t)region_stack_words(levels, threads, opl) * 4) + align16((size_t)cap * kCandBytes) +
-           align16((size_t)(cap + 1) * 4) + align16((size_t)rs * (rs / 32) * 4) + 16 + 64;
+           align16((size_t)(cap + 1) * 4) + align16((size_t)rs * (rs / 32) * 4 * (aa ? 4 : 1)) + 16 + 64;
 }
 
 struct RegionLds {
@@ -522,7 +525,7 @@ struct RegionLds {
     double *ci;
     uint32_t *crng;  // ilo | ihi << 6 | jlo << 12 | jhi << 18 (region pixels)
     uint32_t *cpre;  // exclusive prefix sums of work cells per queued object
-    uint32_t *mask;  // RS rows x RS/32 words
+    uint32_t *mask;  // RS rows x RS/32 words (x4 for anti-aliased output: sub-sample m at m * RS * RS/32)
     int *ctl;        // [0] stack size, [1] queued objects
     uint32_t *scan;  // 16 words
 };
@@ -597,13 +600,21 @@ __device__ inline int region_cells(uint32_t rg) {
     return (jhi - jlo + 1) * ((ihi >> 3) - (ilo >> 3) + 1);
 }
 
-template <int RS, int SEG, int OPL>
+// AA = 0: one bit per pixel, [D(centre) <= r].  AA = 1: Algorithm 1's value
+// 0-4, the number of the pixel's four sub-samples (centre +- 1/4 px in x and
+// y) within r, each against its own nearest object; the region keeps one
+// mask per sub-sample, culls with the samples' reach r + 1/4 px per axis,
+// makes its edge accepts on each sub-sample grid and tests the four
+// sub-samples of every pixel it drains.
+template <int RS, int SEG, int OPL, int AA>
 __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &rq, int64_t t, int reg,
                                              const uint32_t *__restrict__ frontier,
                                              const int32_t *__restrict__ fmeta, uint8_t *__restrict__ out,
                                              int cap, const RegionLds &L) {
     constexpr int NR = 256 / RS;
-    constexpr int W = RS / 32;  // mask words per region row
+    constexpr int W = RS / 32;   // mask words per region row
+    constexpr int MW = RS * W;   // words of one mask
+    constexpr int NM = AA ? 4 : 1;
     const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
     uint32_t *stk = L.stk;
     uint32_t *mask = L.mask;
@@ -611,35 +622,53 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
 
     const int rx = reg % NR, ry = reg / NR;
     const double r = rq.r, r2 = r * r;
+    const double rreach = AA ? r + 0.25 : r;  // per axis, how far from a pixel centre an object can matter
+    // anti-aliased output: centre-distance bounds (Algorithm 1's R1 and R2,
+    // r -+ sqrt(2)/4, each moved 1e-7 px inwards); rin2 < 0 when R1 <= 0
+    const double rin = r - 0.35355339059327373 - 1e-7, rout = r + 0.35355339059327373 + 1e-7;
+    const double rin2 = rin > 0.0 ? rin * rin : -1.0, rout2 = rout * rout;
+    const bool centre_first = AA && r >= 1.0;
     const double S = ldexp(256.0, rq.z);
     const double iS = ldexp(1.0, -8 - rq.z);
     const double ox = 256.0 * (double)rq.x, oy = 256.0 * (double)rq.y;
     const double i0 = (double)(rx * RS), j0 = (double)(ry * RS);
-    const double m = r + kCullPad;
+    const double m = rreach + kCullPad;
     const double qx0 = ((ox + i0) + (0.5 - m)) * iS;
     const double qx1 = ((ox + i0) + ((RS - 0.5) + m)) * iS;
     const double qy0 = ((oy + j0) + (0.5 - m)) * iS;
     const double qy1 = ((oy + j0) + ((RS - 0.5) + m)) * iS;
-    uint8_t *tm = out + t * (int64_t)HV_MASK_BYTES;
+    uint8_t *tm = out + t * (int64_t)(AA ? HV_AA_BYTES : HV_MASK_BYTES);
 
     const int4 fm = reinterpret_cast<const int4 *>(fmeta)[t];
     const int fcount = fm.x, flevel = fm.y;
     const uint64_t reach = (uint64_t)(uint32_t)fm.z | ((uint64_t)(uint32_t)fm.w << 32);
     if (!((reach >> reg) & 1ull)) {
         // no frontier node comes within r of this region: all zero
-        for (int k = tid; k < RS * W; k += nthr)
-            *reinterpret_cast<uint32_t *>(tm + (ry * RS + k / W) * 32 + rx * (RS / 8) + 4 * (k % W)) = 0u;
+        if (AA) {
+            for (int k = tid; k < RS * RS / 4; k += nthr)
+                *reinterpret_cast<uint32_t *>(tm + (ry * RS + k / (RS / 4)) * 256 + rx * RS + 4 * (k % (RS / 4))) = 0u;
+        } else {
+            for (int k = tid; k < RS * W; k += nthr)
+                *reinterpret_cast<uint32_t *>(tm + (ry * RS + k / W) * 32 + rx * (RS / 8) + 4 * (k % W)) = 0u;
+        }
         return;
     }
 
-    for (int k = tid; k < RS * W; k += nthr) mask[k] = 0;
+    for (int k = tid; k < NM * MW; k += nthr) mask[k] = 0;
+    // a range is done once every pixel in it is set in every mask
+    auto range_done = [&](int ilo, int ihi, int jlo, int jhi) -> bool {
+        bool d = range_lit<W>(mask, ilo, ihi, jlo, jhi);
+#pragma unroll
+        for (int mm = 1; mm < NM; ++mm) d = d && range_lit<W>(mask + mm * MW, ilo, ihi, jlo, jhi);
+        return d;
+    };
     if (tid == 0) {
         ctl[0] = 0;
         ctl[1] = 0;
     }
     __syncthreads();
-    // edge accepts keep a margin so that they never claim a pixel whose
-    // distance could round to just above r
+    // accepts keep a margin so that they never claim a sample whose distance
+    // could round to just above r
     const double racc = r - 1e-7, racc2 = racc * racc;
     // Pushes the frontier nodes that meet the region; true when one of them
     // is worth an accept pass: its leaves, at about 4^-level of its size,
@@ -701,31 +730,69 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                 d = L.cd[lo];
                 inv = L.ci[lo];
             }
-            const double wy = (j0 + (double)row + 0.5) - a.y;
-            // only the cell's pixels not lit yet (pixels are only ever set)
-            const int wbase = c0 & ~31;
-            uint32_t todo = (((2u << (c1 - c0)) - 1u) << (c0 - wbase)) & ~mask[row * W + (wbase >> 5)];
-            uint32_t bits = 0;
-            while (todo) {
-                const int ii = wbase + __builtin_ctz(todo);
-                todo &= todo - 1u;
-                const double wx = (i0 + (double)ii + 0.5) - a.x;
-                double d2;
+            // exact FP64 squared distance from a sample (tile-local px) to the object
+            auto dist2 = [&](double px, double py) -> double {
+                const double wx = px - a.x, wy = py - a.y;
                 if (SEG) {
                     double tt = (wx * d.x + wy * d.y) * inv;
                     tt = fmin(fmax(tt, 0.0), 1.0);
                     const double ex = wx - tt * d.x, ey = wy - tt * d.y;
-                    d2 = ex * ex + ey * ey;
-                } else {
-                    d2 = wx * wx + wy * wy;
+                    return ex * ex + ey * ey;
                 }
-                if (d2 <= r2) bits |= 1u << (ii & 31);
+                return wx * wx + wy * wy;
+            };
+            const double cy = j0 + (double)row + 0.5;
+            // only the cell's pixels not done yet (bits are only ever set)
+            const int wbase = c0 & ~31, widx = row * W + (wbase >> 5);
+            uint32_t done = mask[widx];
+#pragma unroll
+            for (int mm = 1; mm < NM; ++mm) done &= mask[mm * MW + widx];
+            uint32_t todo = (((2u << (c1 - c0)) - 1u) << (c0 - wbase)) & ~done;
+            uint32_t bits[NM];
+#pragma unroll
+            for (int mm = 0; mm < NM; ++mm) bits[mm] = 0;
+            while (todo) {
+                const int ii = wbase + __builtin_ctz(todo);
+                const uint32_t bit = 1u << (ii & 31);
+                todo &= todo - 1u;
+                const double cx = i0 + (double)ii + 0.5;
+                if (AA) {
+                    // From r >= 1 on, Algorithm 1's thresholds on the centre's
+                    // distance first: a sub-sample lies sqrt(2)/4 px from it,
+                    // so within rin of the object every sub-sample is within r,
+                    // beyond rout none is (both kept 1e-7 px inside the exact
+                    // bounds).  Otherwise (and for smaller r, where the band
+                    // between them holds nearly every pixel in reach)
+                    // sub-sample mm at (cx -+ 1/4, cy -+ 1/4) is tested itself
+                    // (bit 0 of mm picks +x, bit 1 picks +y).
+                    auto each = [&]() {
+#pragma unroll
+                        for (int mm = 0; mm < NM; ++mm)
+                            if (dist2(cx + ((mm & 1) ? 0.25 : -0.25), cy + ((mm & 2) ? 0.25 : -0.25)) <= r2)
+                                bits[mm] |= bit;
+                    };
+                    if (centre_first) {
+                        const double dc2 = dist2(cx, cy);
+                        if (dc2 <= rin2) {
+#pragma unroll
+                            for (int mm = 0; mm < NM; ++mm) bits[mm] |= bit;
+                        } else if (dc2 <= rout2) {
+                            each();
+                        }
+                    } else {
+                        each();
+                    }
+                } else if (dist2(cx, cy) <= r2) {
+                    bits[0] |= bit;
+                }
             }
-            if (bits) atomicOr(&mask[row * W + (c0 >> 5)], bits);
+#pragma unroll
+            for (int mm = 0; mm < NM; ++mm)
+                if (bits[mm]) atomicOr(&mask[mm * MW + widx], bits[mm]);
         }
         __syncthreads();
         bool full = true;
-        for (int k = tid; k < RS * W; k += nthr) full &= mask[k] == 0xffffffffu;
+        for (int k = tid; k < NM * MW; k += nthr) full &= mask[k] == 0xffffffffu;
         const bool all = __syncthreads_and(full);
         if (tid == 0) ctl[1] = 0;
         __syncthreads();
@@ -791,13 +858,13 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     const double bx0 = nb.x * S - ox, bx1 = nb.z * S - ox;
                     const double by0 = nb.y * S - oy, by1 = nb.w * S - oy;
                     int ilo, ihi, jlo, jhi;
-                    push = px_range<RS>(bx0, bx1, by0, by1, r, i0, j0, ilo, ihi, jlo, jhi);
+                    push = px_range<RS>(bx0, bx1, by0, by1, rreach, i0, j0, ilo, ihi, jlo, jhi);
                     const double bw = bx1 - bx0, bh = by1 - by0;
                     const double diag2 = bw * bw + bh * bh;
                     const bool small = racc > 0.0 && bw <= 2.0 * racc && bh <= 2.0 * racc;
                     // a child whose pixel range is all lit can add nothing:
                     // neither accepts nor objects
-                    if (push && range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
+                    if (push && range_done(ilo, ihi, jlo, jhi)) push = false;
                     if (push && small) {
                         // Edge accept.  A node box is the exact bounding box of
                         // its objects' coordinates (points, segment endpoints),
@@ -821,39 +888,52 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         // r^2 - ra^2 = 2 r 1e-3 - 1e-6 for every r in (1e-3, 64].
                         // No accept claims a centre beyond r; pixels near an
                         // accept's edge fall to the exact FP64 test.
+                        // For anti-aliased output the same test runs on each of
+                        // the four sub-sample grids (centres shifted by -+1/4
+                        // px in x and y) and lights that sub-sample's mask.
                         const float ra = (float)(r - kAcceptMargin);
                         const float ra2 = ra * ra;
                         const float fx0 = (float)bx0, fx1 = (float)bx1, fy0 = (float)by0, fy1 = (float)by1;
-                        const float fc0 = (float)(i0 + 0.5);  // centre of region column 0 (exact)
-                        auto run = [&](float lo, float hi) -> uint64_t {
-                            const int a0 = max((int)ceilf(lo - fc0 + 1e-4f), ilo);
-                            const int a1 = min((int)floorf(hi - fc0 - 1e-4f), ihi);
-                            if (a0 > a1) return 0ull;
-                            return (a1 - a0 == 63 ? ~0ull : ((1ull << (a1 - a0 + 1)) - 1ull)) << a0;
-                        };
-                        for (int jj = jlo; jj <= jhi && ra > 0.0f; ++jj) {
-                            const float cy = (float)(j0 + (double)jj + 0.5);  // exact
-                            const float ey0 = fabsf(cy - fy0), ey1 = fabsf(cy - fy1);
-                            const float dyn = fminf(ey0, ey1), dyf = fmaxf(ey0, ey1);
-                            const float rn = ra2 - dyn * dyn;
-                            if (rn < 0.0f) continue;
-                            const float b = __builtin_amdgcn_sqrtf(rn);
-                            uint64_t bits = run(fx1 - b, fx0 + b);
-                            const float rf = ra2 - dyf * dyf;
-                            if (rf >= 0.0f) {
-                                const float a = __builtin_amdgcn_sqrtf(rf);
-                                bits |= run(fx0 - a, fx0 + a) | run(fx1 - a, fx1 + a);
-                            }
+                        // rows of samples: one per pixel row, or two (-+1/4) for
+                        // anti-aliased output, each serving its two sub-sample
+                        // columns (-+1/4), which share the row's runs
 #pragma unroll
-                            for (int wd = 0; wd < W; ++wd) {
-                                const uint32_t wb = (uint32_t)(bits >> (32 * wd));
-                                if (wb) {
-                                    atomicOr(&mask[jj * W + wd], wb);
-                                    accepted = true;
+                        for (int sy = 0; sy < (AA ? 2 : 1); ++sy) {
+                            const float syo = AA ? (sy ? 0.25f : -0.25f) : 0.0f;
+                            for (int jj = jlo; jj <= jhi && ra > 0.0f; ++jj) {
+                                const float cy = (float)(j0 + (double)jj + 0.5) + syo;  // exact
+                                const float ey0 = fabsf(cy - fy0), ey1 = fabsf(cy - fy1);
+                                const float dyn = fminf(ey0, ey1), dyf = fmaxf(ey0, ey1);
+                                const float rn = ra2 - dyn * dyn;
+                                if (rn < 0.0f) continue;
+                                const float b = __builtin_amdgcn_sqrtf(rn);
+                                const float rf = ra2 - dyf * dyf;
+                                const float a = rf >= 0.0f ? __builtin_amdgcn_sqrtf(rf) : -1.0f;
+#pragma unroll
+                                for (int sx = 0; sx < (AA ? 2 : 1); ++sx) {
+                                    // sample of region column 0 (exact)
+                                    const float fc0 = (float)(i0 + 0.5) + (AA ? (sx ? 0.25f : -0.25f) : 0.0f);
+                                    auto run = [&](float lo, float hi) -> uint64_t {
+                                        const int a0 = max((int)ceilf(lo - fc0 + 1e-4f), ilo);
+                                        const int a1 = min((int)floorf(hi - fc0 - 1e-4f), ihi);
+                                        if (a0 > a1) return 0ull;
+                                        return (a1 - a0 == 63 ? ~0ull : ((1ull << (a1 - a0 + 1)) - 1ull)) << a0;
+                                    };
+                                    uint64_t bits = run(fx1 - b, fx0 + b);
+                                    if (a >= 0.0f) bits |= run(fx0 - a, fx0 + a) | run(fx1 - a, fx1 + a);
+                                    const int mm = AA ? 2 * sy + sx : 0;
+#pragma unroll
+                                    for (int wd = 0; wd < W; ++wd) {
+                                        const uint32_t wb = (uint32_t)(bits >> (32 * wd));
+                                        if (wb) {
+                                            atomicOr(&mask[mm * MW + jj * W + wd], wb);
+                                            accepted = true;
+                                        }
+                                    }
                                 }
                             }
                         }
-                        if (range_lit<W>(mask, ilo, ihi, jlo, jhi)) push = false;
+                        if (range_done(ilo, ihi, jlo, jhi)) push = false;
                     }
                     // The accept pass stops at leaves and at nodes whose diagonal
                     // is at most 1.5 racc.  A box's edge accepts light every pixel
@@ -906,13 +986,13 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     // tile-local pixel frame; scaling by S is exact
                     ua = ax * S - ox; va = ay * S - oy;
                     ub = bxx * S - ox; vb = byy * S - oy;
-                    // region pixels whose centre lies within r of the object's box
-                    const double flo_i = fmax(ceil(fmin(ua, ub) - r - 0.5 - i0 - kRangeEps), 0.0);
-                    const double fhi_i = fmin(floor(fmax(ua, ub) + r - 0.5 - i0 + kRangeEps), RS - 1.0);
-                    const double flo_j = fmax(ceil(fmin(va, vb) - r - 0.5 - j0 - kRangeEps), 0.0);
-                    const double fhi_j = fmin(floor(fmax(va, vb) + r - 0.5 - j0 + kRangeEps), RS - 1.0);
+                    // region pixels that have a sample within r of the object's box
+                    const double flo_i = fmax(ceil(fmin(ua, ub) - rreach - 0.5 - i0 - kRangeEps), 0.0);
+                    const double fhi_i = fmin(floor(fmax(ua, ub) + rreach - 0.5 - i0 + kRangeEps), RS - 1.0);
+                    const double flo_j = fmax(ceil(fmin(va, vb) - rreach - 0.5 - j0 - kRangeEps), 0.0);
+                    const double fhi_j = fmin(floor(fmax(va, vb) + rreach - 0.5 - j0 + kRangeEps), RS - 1.0);
                     if (flo_i <= fhi_i && flo_j <= fhi_j &&
-                        !range_lit<W>(mask, (int)flo_i, (int)fhi_i, (int)flo_j, (int)fhi_j)) {
+                        !range_done((int)flo_i, (int)fhi_i, (int)flo_j, (int)fhi_j)) {
                         keep = true;
                         rg = (uint32_t)flo_i | ((uint32_t)fhi_i << 6) | ((uint32_t)flo_j << 12) |
                              ((uint32_t)fhi_j << 18);
@@ -934,7 +1014,7 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         if (__syncthreads_or(accepted)) {
             // accepts may have lit the whole region
             bool full = true;
-            for (int k = tid; k < RS * W; k += nthr) full &= mask[k] == 0xffffffffu;
+            for (int k = tid; k < NM * MW; k += nthr) full &= mask[k] == 0xffffffffu;
             if (__syncthreads_and(full)) {
                 done = true;
                 break;
@@ -947,14 +1027,31 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
     }
     if (!done && ctl[1] > 0) drain();
     __syncthreads();
-    for (int k = tid; k < RS * W; k += nthr) {
-        const int row = k / W, wd = k % W;
-        *reinterpret_cast<uint32_t *>(tm + (ry * RS + row) * 32 + rx * (RS / 8) + 4 * wd) = mask[k];
+    if (AA) {
+        // one byte per pixel: the number of its sub-samples within r; a
+        // thread writes four neighbouring pixels
+        for (int k = tid; k < RS * RS / 4; k += nthr) {
+            const int row = k / (RS / 4), col = 4 * (k % (RS / 4)), widx = row * W + (col >> 5);
+            uint32_t v = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t c = 0;
+#pragma unroll
+                for (int mm = 0; mm < NM; ++mm) c += (mask[mm * MW + widx] >> ((col + q) & 31)) & 1u;
+                v |= c << (8 * q);
+            }
+            *reinterpret_cast<uint32_t *>(tm + (ry * RS + row) * 256 + rx * RS + col) = v;
+        }
+    } else {
+        for (int k = tid; k < RS * W; k += nthr) {
+            const int row = k / W, wd = k % W;
+            *reinterpret_cast<uint32_t *>(tm + (ry * RS + row) * 32 + rx * (RS / 8) + 4 * wd) = mask[k];
+        }
     }
     __syncthreads();
 }
 
-template <int RS, int OPL>
+template <int RS, int OPL, int AA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_query_region(DevBatch B, int cap, int max_levels) {
     extern __shared__ double4 smem[];
     constexpr int RPT = (256 / RS) * (256 / RS);
@@ -968,18 +1065,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     L.crng = reinterpret_cast<uint32_t *>(L.ci + cap);
     L.cpre = reinterpret_cast<uint32_t *>(cb + align16((size_t)cap * kCandBytes));
     L.mask = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.cpre) + align16((size_t)(cap + 1) * 4));
-    L.ctl = reinterpret_cast<int *>(L.mask + RS * (RS / 32));
+    L.ctl = reinterpret_cast<int *>(L.mask + RS * (RS / 32) * (AA ? 4 : 1));
     L.scan = reinterpret_cast<uint32_t *>(L.ctl + 4);
     uint8_t *const out = B.hdr->out;
-    zero_empty_tiles(B, out);
+    zero_empty_tiles(B, out, AA ? HV_AA_BYTES : HV_MASK_BYTES);
     const ItemMap im(B.hdr->counter, RPT);
     for (int64_t u = im.first; u < im.n; u += im.step) {
         const int64_t t = B.list[im.pos(u, RPT)];
         const int reg = (int)(u % RPT);
         const DevReq rq = B.reqs[t];
         const DevIndex ix = B.ixs[rq.index];
-        if (ix.seg) region_query<RS, 1, OPL>(ix, rq, t, reg, B.frontier, B.fmeta, out, cap, L);
-        else region_query<RS, 0, OPL>(ix, rq, t, reg, B.frontier, B.fmeta, out, cap, L);
+        if (ix.seg) region_query<RS, 1, OPL, AA>(ix, rq, t, reg, B.frontier, B.fmeta, out, cap, L);
+        else region_query<RS, 0, OPL, AA>(ix, rq, t, reg, B.frontier, B.fmeta, out, cap, L);
         if (threadIdx.x == 0) part_done(B, t, RPT);
     }
 }
@@ -1289,42 +1386,19 @@ __global__ __launch_bounds__(256) void k_fill_region(DevBatch B, int cap, int ma
     }
 }
 
-// ------------------------------------------------------------ anti-aliasing
-// Algorithm 1's value 0-4 per pixel counts the pixel's four sub-samples
-// (centre +- 1/4 px in x and y) within r.  Those sub-samples are exactly the
-// pixel centres of the tile's four children one zoom deeper, where r is 2r
-// (every coordinate doubles exactly), so the value is the sum of the pixel's
-// 2 x 2 bits in the children's masks.  child_masks: 4 per request, child
-// 2 * dy + dx = tile (z + 1, 2x + dx, 2y + dy).  One thread per four output
-// pixels: child row bytes b0 (row 2j') and b1 (row 2j' + 1) hold the 8
-// sub-sample columns of those pixels.
-__global__ __launch_bounds__(256) void k_aa_reduce(const uint8_t *__restrict__ child_masks, int64_t n,
-                                                   uint8_t *__restrict__ out) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n * (HV_AA_BYTES / 4)) return;
-    const int64_t k = g / (HV_AA_BYTES / 4);
-    const int w = (int)(g % (HV_AA_BYTES / 4));
-    const int j = w >> 6, q = w & 63;           // row, group of pixels 4q .. 4q + 3
-    const int dy = j >> 7, dx = q >> 5;
-    const uint8_t *c = child_masks + (k * 4 + dy * 2 + dx) * (int64_t)HV_MASK_BYTES;
-    const int row = 2 * (j & 127), col = q & 31;
-    const uint32_t b0 = c[row * 32 + col], b1 = c[(row + 1) * 32 + col];
-    uint32_t v = 0;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-        v |= (uint32_t)(__popc((b0 >> (2 * m)) & 3u) + __popc((b1 >> (2 * m)) & 3u)) << (8 * m);
-    reinterpret_cast<uint32_t *>(out + k * (int64_t)HV_AA_BYTES)[w] = v;
-}
-
 using RegionKernel = void (*)(DevBatch, int, int);
 
-RegionKernel region_kernel(const LaunchShape &s) {
-    if (s.region == 32) return s.opl == 4 ? k_query_region<32, 4> : s.opl == 2 ? k_query_region<32, 2> : k_query_region<32, 1>;
-    return s.opl == 4 ? k_query_region<64, 4> : s.opl == 2 ? k_query_region<64, 2> : k_query_region<64, 1>;
+template <int AA>
+RegionKernel region_kernel_aa(const LaunchShape &s) {
+    if (s.region == 32)
+        return s.opl == 4 ? k_query_region<32, 4, AA> : s.opl == 2 ? k_query_region<32, 2, AA> : k_query_region<32, 1, AA>;
+    return s.opl == 4 ? k_query_region<64, 4, AA> : s.opl == 2 ? k_query_region<64, 2, AA> : k_query_region<64, 1, AA>;
 }
 
+RegionKernel region_kernel(const LaunchShape &s) { return s.aa ? region_kernel_aa<1>(s) : region_kernel_aa<0>(s); }
+
 struct GridKey {
-    int device, block, waves, region, opl, fill;
+    int device, block, waves, region, opl, fill, aa;
     size_t lds;
     int grid;
 };
@@ -1333,7 +1407,7 @@ struct GridKey {
 
 size_t query_lds_bytes(const LaunchShape &s, int max_levels) {
     if (s.fill) return fill_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region);
-    if (s.region) return region_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region, s.opl);
+    if (s.region) return region_lds_bytes(s.cand_cap, max_levels, 64 * s.waves, s.region, s.opl, s.aa);
     return (size_t)s.waves * wave_lds_bytes(s.cand_cap, max_levels, s.block);
 }
 
@@ -1389,7 +1463,8 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
     std::lock_guard<std::mutex> g(mu);
     for (int k = 0; k < ncache; ++k)
         if (cache[k].device == dev && cache[k].block == s.block && cache[k].waves == s.waves &&
-            cache[k].region == s.region && cache[k].opl == s.opl && cache[k].fill == s.fill && cache[k].lds == lds)
+            cache[k].region == s.region && cache[k].opl == s.opl && cache[k].fill == s.fill && cache[k].aa == s.aa &&
+            cache[k].lds == lds)
             return cache[k].grid;
     int per_cu = 0, cus = 0;
     const int thr = 64 * s.waves;
@@ -1407,15 +1482,8 @@ int persistent_grid(const LaunchShape &s, int max_levels) {
     // ten times what fits at once: the dispatcher then hands out the
     // remaining workgroups as others finish, which evens out uneven blocks
     const int grid = 10 * per_cu * cus;
-    if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, s.region, s.opl, s.fill, lds, grid};
+    if (ncache < 16) cache[ncache++] = GridKey{dev, s.block, s.waves, s.region, s.opl, s.fill, s.aa, lds, grid};
     return grid;
-}
-
-hipError_t launch_aa_reduce(const uint8_t *child_masks, int64_t n, uint8_t *out, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    const int64_t words = n * (HV_AA_BYTES / 4);
-    hipLaunchKernelGGL(k_aa_reduce, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, child_masks, n, out);
-    return hipGetLastError();
 }
 
 hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, const LaunchShape &s,
@@ -1425,7 +1493,8 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, 
     const DevBatch B = device_batch(w, dws);
     hipError_t e;
     if (marks && (e = hipEventRecord(marks[0], st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B, s.region, s.cull);
+    hipLaunchKernelGGL(k_tile_frontier, dim3((uint32_t)((n_req + 3) / 4)), dim3(256), 0, st, B, s.region, s.cull,
+                       s.aa ? 0.25 : 0.0);
     if (marks && (e = hipEventRecord(marks[1], st)) != hipSuccess) return e;
     const size_t lds = query_lds_bytes(s, max_levels);
     // never more workgroups than there are blocks (or regions) to render

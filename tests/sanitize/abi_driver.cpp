@@ -67,7 +67,8 @@ int main() {
     CHECK(hv_render_batch(rq, 0, nullptr, nullptr) == HV_OK);
     CHECK(hv_render_batch_aa(rq, 3, dummy, nullptr) == HV_EINVAL);
     rq[2] = hv_request{e, 22, 0, 0, 0, 1.0};
-    CHECK(hv_render_batch_aa(rq, 3, dummy, nullptr) == HV_EINVAL);         // no room one zoom deeper
+    CHECK(hv_render_batch_aa(rq, 3, dummy, nullptr) == HV_EINVAL);         // output not device memory
+    CHECK(hv_render_batch_aa(rq, 0, nullptr, nullptr) == HV_OK);
     std::vector<hv_request> many(HV_NOALLOC_MAX_REQUESTS + 1, hv_request{e, 3, 1, 1, 0, 1.0});
     CHECK(hv_render_batch_noalloc(many.data(), (int64_t)many.size(), dummy, nullptr) == HV_EINVAL);
     CHECK(hv_render_batch_noalloc(rq, -1, dummy, nullptr) == HV_EINVAL);

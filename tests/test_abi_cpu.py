@@ -108,7 +108,7 @@ def test_batch_validation_before_any_device_call(hv):
         with pytest.raises(hv.HvError, match="empty"):
             hv.hv_autotune(hv.requests(h, np.zeros((0, 3)), 1.0), 1)
         assert hv.hv_tuned_launch(hv.requests(h, [(3, 1, 1)], 1.0)) is None
-        for reqs, msg in [(hv.requests(h, [(22, 0, 0)], 1.0), "z <= 21"),
+        for reqs, msg in [(hv.requests(h, [(23, 0, 0)], 1.0), "zoom"),
                           (hv.requests(h, [(3, 8, 1)], 1.0), "x or y"),
                           (hv.requests(h, [(3, 1, 1)], 65.0), "r_px")]:
             with pytest.raises(hv.HvError, match=msg):

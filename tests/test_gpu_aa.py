@@ -66,7 +66,9 @@ def test_aa_points_c1_all_tiles(hv, torch):
     ix = oracle.OracleIndex(pts, oracle.POINTS)
     got = render_aa(hv, torch, h, tiles, r)
     check_aa(got, ix.render_aa(tiles, r), "aa c1", paper=ix.render_aa(tiles, r, mode="paper"))
-    for L in (dict(region=64, waves_per_wg=4, cand_cap=256), dict(region=0, block=16, waves_per_wg=2)):
+    for L in (dict(region=64, waves_per_wg=4, cand_cap=256), dict(region=0, block=16, waves_per_wg=2),
+              dict(region=32, waves_per_wg=1, objs_per_lane=2, cand_cap=128),
+              dict(region=32, waves_per_wg=2, objs_per_lane=4, cand_cap=512, grid_wgs=7)):
         assert np.array_equal(render_aa(hv, torch, h, tiles, r, launch=L), got), L
     hv.hv_free(h)
 
@@ -101,11 +103,13 @@ def test_aa_mixed_batch_and_extremes(hv, torch):
     pts = hvgen.gen_c1_points(n=5000)
     hs = [build(hv, torch, segs, hv.HV_SEGMENTS), build(hv, torch, pts, hv.HV_POINTS)]
     ixs = [oracle.OracleIndex(segs, oracle.SEGMENTS), oracle.OracleIndex(pts, oracle.POINTS)]
-    # a point's own tile at z = 21 (the deepest allowed), tiny and large radii
+    # a point's own tile at z = 21 and z = 22 (the deepest zoom), tiny and large radii
     X, Y = oracle.project(pts[:1])
     deep = (21, int(X[0] * 2 ** 21), int(Y[0] * 2 ** 21))
+    deepest = (22, int(X[0] * 2 ** 22), int(Y[0] * 2 ** 22))
     cases = [(1, (0, 0, 0), 0.1), (1, (0, 0, 0), 64.0), (1, deep, 0.3), (1, deep, 3.0), (0, (3, 4, 3), 2.5),
-             (0, (5, 9, 12), 0.5), (1, (4, 7, 6), 1.0), (0, (0, 0, 0), 0.5)]
+             (0, (5, 9, 12), 0.5), (1, (4, 7, 6), 1.0), (0, (0, 0, 0), 0.5), (1, deepest, 0.36),
+             (1, deepest, 2.0)]
     ds = np.array([c[0] for c in cases])
     tiles = np.array([c[1] for c in cases])
     rs = np.array([c[2] for c in cases])
