@@ -40,3 +40,29 @@ def hilbert_np(x: np.ndarray, y: np.ndarray, bits: int) -> np.ndarray:
         swap = ~ry
         x, y = np.where(swap, y, x), np.where(swap, x, y)
     return d
+
+
+def input_fingerprint(rows_strided: np.ndarray, n_rows: int, tiles: np.ndarray, r: np.ndarray) -> str:
+    """SHA-256 of a generated workload: every 1000th object row (rows 0, 1000,
+    ...; passed in, so that a chunked generator can assemble them), the object
+    count and the requests.  Ties a stored oracle result to the inputs it was
+    computed from."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.int64(n_rows).tobytes())
+    h.update(np.ascontiguousarray(rows_strided, dtype=np.float64).tobytes())
+    h.update(np.ascontiguousarray(tiles, dtype=np.int32).tobytes())
+    h.update(np.ascontiguousarray(r, dtype=np.float64).tobytes())
+    return h.hexdigest()
+
+
+def stratified_sample(tiles: np.ndarray, per_zoom: int, seed: int, zmin: int = 0) -> np.ndarray:
+    """Request indices: per_zoom drawn at random at every zoom >= zmin present."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for z in np.unique(tiles[:, 0]):
+        if z < zmin:
+            continue
+        idx = np.nonzero(tiles[:, 0] == z)[0]
+        out.append(np.sort(rng.permutation(idx)[:per_zoom]))
+    return np.concatenate(out) if out else np.zeros(0, dtype=np.int64)

@@ -1,15 +1,21 @@
 """The full-size workloads in the launch the benchmark times (the graph-
-captured batcher, default shape): 1e9 clustered points with 10,000 requests
-at zooms 0-18, and 2e8 polygon edges with 4,096 requests at zooms 2-20, as
-distance masks and as polygon fills (hv_render_fill, default shape).
+captured batcher; for the 2e8 edges the autotuned shape, as bench.py picks
+it): 1e9 clustered points with 10,000 requests at zooms 0-18, and 2e8 polygon
+edges with 4,096 requests at zooms 2-20, as distance masks and as polygon
+fills (hv_render_fill, default shape).
 
-At this size the oracle cannot index everything on the host, so it checks
-sampled tiles at zoom >= 10 over the objects whose bounding box comes within
-4 px of them (a superset of every object that can reach the tile), and
-properties that hold at any size cover every tile: the masks of the whole
-set are the OR of the masks of its two halves, and a point's own pixel is
-lit for r >= sqrt(2)/2."""
+The oracle's masks for zoom-stratified samples of both -- 27 requests per
+zoom: all of zooms 2-20 for the edges, zooms 3-18 for the points -- are
+stored in tests/golden/fullsize_*.npz by tests/golden/make_fullsize_parity.py
+(which calls only the oracle and the generators), with a fingerprint of the
+inputs that is checked here first.  Every sampled pixel the oracle does not
+flag as ambiguous must match, and the ambiguous pixels, counted over the
+whole sample, must stay below 1e-6 of the pixels checked.  Properties that
+hold at any size cover every tile: the masks of the whole set are the OR of
+the masks of its two halves, and a point's own pixel is lit for r >=
+sqrt(2)/2."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,9 +23,11 @@ import pytest
 import hvgen
 import oracle
 from gpu_common import log
-from helpers import AMBIGUOUS_LIMIT, parity, unpack_masks
+from helpers import AMBIGUOUS_LIMIT, input_fingerprint, parity, unpack_masks
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -44,12 +52,13 @@ def _build(hv, torch, objs, kind):
     return h
 
 
-def _batched(hv, torch, hs, tiles, r):
-    """All requests through one graph-captured batcher run (default shape)."""
+def _batched(hv, torch, hs, tiles, r, launch=None):
+    """All requests through one graph-captured batcher run (default shape, or
+    the given launch)."""
     n = len(tiles)
     reqs = hv.requests(np.broadcast_to(np.asarray(hs, dtype=np.uint64), (n,)), tiles, r)
     levels = max(hv.hv_index_info(int(h))["levels"] for h in np.atleast_1d(hs))
-    b = hv.hv_batcher_create(n, max_indexes=1, max_levels=levels)
+    b = hv.hv_batcher_create(n, max_indexes=1, max_levels=levels, launch=launch)
     out = torch.empty((n, 8192), dtype=torch.uint8, device="cuda")
     out.fill_(0x5A)
     hv.hv_batcher_run(b, reqs, out)
@@ -74,28 +83,28 @@ def _deep_sample(tiles, k, zmin=10):
     return deep[np.linspace(0, len(deep) - 1, k).astype(int)]
 
 
-def _check_sample(packed, objs, kind, tiles, r, pick, what):
-    for t in pick:
-        z, x, y = (int(v) for v in tiles[t])
-        lon0, lon1, lat0, lat1 = _lonlat_box(z, x, y, 4.0 + float(np.max(r)))
-        if kind == oracle.POINTS:
-            sel = (objs[:, 0] >= lon0) & (objs[:, 0] <= lon1) & (objs[:, 1] >= lat0) & (objs[:, 1] <= lat1)
-        else:
-            lo_x = np.minimum(objs[:, 0], objs[:, 2])
-            hi_x = np.maximum(objs[:, 0], objs[:, 2])
-            lo_y = np.minimum(objs[:, 1], objs[:, 3])
-            hi_y = np.maximum(objs[:, 1], objs[:, 3])
-            sel = (hi_x >= lon0) & (lo_x <= lon1) & (hi_y >= lat0) & (lo_y <= lat1)
-        sub = objs[sel]
-        got = unpack_masks(packed[t:t + 1])
-        if sub.shape[0] == 0:
-            assert not got.any(), (what, t)
-            continue
-        tri = oracle.OracleIndex(sub, kind).render(tiles[t:t + 1], float(np.asarray(r)[t]))["tri"]
-        mism, amb, lit = parity(got, tri)
-        log(f"{what} tile {tuple(tiles[t])}: objects near={sub.shape[0]} lit={lit} ambiguous={amb} mismatches={mism}")
-        assert mism == 0, (what, tuple(tiles[t]))
-        assert amb <= AMBIGUOUS_LIMIT * 65536 + 1e-9 or amb <= 2, (what, tuple(tiles[t]), amb)
+def _check_golden(packed, name, objs, tiles, r, what):
+    """The GPU masks of the stored sample against the oracle's stored masks."""
+    g = np.load(os.path.join(GOLDEN, f"fullsize_{name}.npz"))
+    fp = input_fingerprint(objs[::1000], objs.shape[0], tiles, r)
+    assert str(g["fingerprint"]) == fp, f"{what}: the inputs differ from those the stored oracle masks were made from"
+    idx = g["idx"]
+    assert np.array_equal(g["tiles"], tiles[idx]) and np.array_equal(g["r"], r[idx])
+    lit = np.unpackbits(g["lit"], axis=-1, bitorder="little").astype(bool)
+    amb = np.unpackbits(g["amb"], axis=-1, bitorder="little").astype(bool)
+    tri = np.where(amb, 2, np.where(lit, 1, 0)).astype(np.uint8)
+    got = unpack_masks(packed[idx])
+    mism_per = ((got.astype(bool) != lit) & ~amb).reshape(len(idx), -1).sum(1)
+    n_amb = int(amb.sum())
+    for z in np.unique(tiles[idx, 0]):
+        sel = tiles[idx, 0] == z
+        log(f"{what} z{z}: {int(sel.sum())} tiles, lit={int(lit[sel].sum())} ambiguous={int(amb[sel].sum())} "
+            f"mismatches={int(mism_per[sel].sum())}")
+    bad = idx[mism_per > 0]
+    assert len(bad) == 0, f"{what}: non-ambiguous mismatches in requests {bad[:10].tolist()}"
+    px = tri.size
+    log(f"{what}: {len(idx)} sampled tiles, {px} pixels, {n_amb} ambiguous ({n_amb / px:.2e})")
+    assert n_amb <= AMBIGUOUS_LIMIT * px, f"{what}: {n_amb} ambiguous pixels over {px}"
 
 
 def test_c3_full_size(hv, torch):
@@ -129,9 +138,8 @@ def test_c3_full_size(hv, torch):
     i = np.minimum((X * S - 256.0 * own[:, 1]).astype(np.int64), 255)
     j = np.minimum((Y * S - 256.0 * own[:, 2]).astype(np.int64), 255)
     assert m[np.arange(512), j, i].all(), "a point's own pixel is lit"
-    pick = _deep_sample(tiles, 6)
-    log(f"c3 full size: oracle on {len(pick)} sampled tiles")
-    _check_sample(full, pts, oracle.POINTS, tiles, r, pick, "c3-full")
+    log("c3 full size: stored oracle masks of 27 requests per zoom at zooms 3-18")
+    _check_golden(full, "c3", pts, tiles, r, "c3-full")
 
 
 def test_c4_full_size(hv, torch):
@@ -139,8 +147,14 @@ def test_c4_full_size(hv, torch):
     edges = hvgen.gen_c4_edges()
     tiles, r = hvgen.c4_requests(edges, n=4096)
     h = _build(hv, torch, edges, hv.HV_POLYGON_EDGES)
-    log("c4 full size: render 4096 requests")
-    full = _batched(hv, torch, h, tiles, r)
+    log("c4 full size: autotune, then render 4096 requests in the tuned shape")
+    reqs = hv.requests(h, tiles, r)
+    scratch = torch.empty((len(tiles), 8192), dtype=torch.uint8, device="cuda")
+    launch, _ = hv.hv_autotune(reqs, scratch)
+    del scratch
+    log(f"c4 full size: tuned launch {launch}")
+    full = _batched(hv, torch, h, tiles, r, launch)
+    assert np.array_equal(full, _batched(hv, torch, h, tiles, r)), "tuned and default shapes differ"
     hv.hv_free(h)
     n = edges.shape[0]
     log("c4 full size: halves")
@@ -151,9 +165,8 @@ def test_c4_full_size(hv, torch):
     b = _batched(hv, torch, hb, tiles, r)
     hv.hv_free(hb)
     assert np.array_equal(full, a | b), "whole set = OR of its halves"
-    pick = _deep_sample(tiles, 6)
-    log(f"c4 full size: oracle on {len(pick)} sampled tiles")
-    _check_sample(full, edges, oracle.POLYGON_EDGES, tiles, r, pick, "c4-full")
+    log("c4 full size: stored oracle masks of 27 requests per zoom at zooms 2-20")
+    _check_golden(full, "c4", edges, tiles, r, "c4-full")
 
 
 def _check_fill_sample(packed, edges, first, tiles, pick, what):

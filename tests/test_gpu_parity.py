@@ -11,7 +11,7 @@ import pytest
 import hvgen
 import oracle
 from gpu_common import build, log, render, render_mixed
-from helpers import AMBIGUOUS_LIMIT, parity
+from helpers import AMBIGUOUS_LIMIT, parity, unpack_masks
 from brute import merc01
 
 pytestmark = pytest.mark.gpu
@@ -71,27 +71,33 @@ def test_c2_linestrings_reduced(hv, torch):
     hv.hv_free(h)
 
 
-def test_c2_linestrings_full_sampled(hv, torch):
-    """Full 10M-segment workload, all 4096 z6 tiles in one launch (the
-    benchmark's launch); the oracle checks a sample of 64 tiles."""
+def test_c2_linestrings_full_all_tiles(hv, torch):
+    """Full 10M-segment workload: all 4096 z6 tiles in one graph-captured
+    batcher launch (the benchmark's launch) and in one plain render, both
+    checked against the oracle on every tile; the ambiguous pixels are
+    counted over all 268M pixels."""
     segs = hvgen.gen_c2_segments()
     tiles, r = hvgen.c2_requests()
     log("c2-full build")
     h = build(hv, torch, segs, hv.HV_SEGMENTS)
-    log("c2-full render 4096 tiles")
-    bits = render(hv, torch, h, tiles, r)
+    log("c2-full render 4096 tiles: batcher and plain call")
+    reqs = hv.requests(h, tiles, r)
+    levels = hv.hv_index_info(h)["levels"]
+    b = hv.hv_batcher_create(len(tiles), max_indexes=1, max_levels=levels)
+    out = torch.empty((len(tiles), 8192), dtype=torch.uint8, device="cuda")
+    out.fill_(0x5A)
+    hv.hv_batcher_run(b, reqs, out)
+    torch.cuda.synchronize()
+    hv.hv_batcher_free(b)
+    bits = unpack_masks(out.cpu().numpy())
+    del out
+    plain = render(hv, torch, h, tiles, r)
     hv.hv_free(h)
-    m = merc01(segs[::50, :2])
-    cnt = np.zeros((64, 64), np.int64)
-    np.add.at(cnt, (np.clip((m[:, 1] * 64).astype(int), 0, 63), np.clip((m[:, 0] * 64).astype(int), 0, 63)), 1)
-    dense = np.argsort(cnt.ravel())[::-1][:32]           # row-major index y * 64 + x
-    rng = np.random.default_rng(22)
-    pick = np.unique(np.concatenate([dense, rng.integers(0, 4096, 32)]))
-    log(f"c2-full oracle on {len(pick)} tiles")
-    ix = oracle.OracleIndex(segs, oracle.SEGMENTS)
-    tri = ix.render(tiles[pick], r)["tri"]
-    _assert_parity(bits[pick], tri, "c2-full-sample")
-    # tiles with no data nearby are empty: any lit pixel needs a segment within 0.5 px
+    assert np.array_equal(bits, plain), "batcher and plain call differ"
+    del plain
+    log("c2-full oracle on all 4096 tiles")
+    tri = oracle.OracleIndex(segs, oracle.SEGMENTS).render(tiles, r, want_bit=False)["tri"]
+    _assert_parity(bits, tri, "c2-full")
     assert bits.sum() > 0
 
 
