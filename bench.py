@@ -48,7 +48,7 @@ METRIC = "256×256 tiles/sec at 1 GPU + p50/p99 tile latency; batched vs per-til
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 WORK_FILE = os.path.join(ROOT, "tests", "golden", "algorithmic_work.json")
-COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_query_*.json")
+COUNTERS_GLOB = os.path.join(ROOT, "profiles", "counters_query*.json")
 QUERY_SOURCE = os.path.join(ROOT, "paper_2005_12489_amd", "csrc", "hv_query.hip")
 
 WORKLOADS = {
@@ -106,11 +106,11 @@ def make_workload(key: str, scale: float = 1.0):
 def query_kernel_name(launch) -> str:
     """Name of the query kernel a launch shape runs (as profilers show it)."""
     if not launch:
-        return "k_query_region<32, 2>"      # the default shape, whatever its waves per workgroup
+        return "k_query_region<32, 2, 0>"   # the default shape, whatever its waves per workgroup
     L = launch
     region = L.get("region", 0)
     if region:
-        return f"k_query_region<{region}, {L.get('objs_per_lane', 1) or 1}>"
+        return f"k_query_region<{region}, {L.get('objs_per_lane', 1) or 1}, 0>"
     return f"k_query<{L.get('block', 16) or 16}>"
 
 

@@ -24,9 +24,9 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def test_query_kernel_names():
     b = _bench_module()
-    assert b.query_kernel_name(None) == "k_query_region<32, 2>"
-    assert b.query_kernel_name({"region": 64, "objs_per_lane": 1}) == "k_query_region<64, 1>"
-    assert b.query_kernel_name({"region": 32, "objs_per_lane": 0}) == "k_query_region<32, 1>"
+    assert b.query_kernel_name(None) == "k_query_region<32, 2, 0>"
+    assert b.query_kernel_name({"region": 64, "objs_per_lane": 1}) == "k_query_region<64, 1, 0>"
+    assert b.query_kernel_name({"region": 32, "objs_per_lane": 0}) == "k_query_region<32, 1, 0>"
     assert b.query_kernel_name({"region": 0, "block": 8}) == "k_query<8>"
     assert b.query_kernel_name({"block": 0}) == "k_query<16>"
 
@@ -58,14 +58,14 @@ def test_counters_are_matched_on_the_full_launch(tmp_path, monkeypatch):
     b = _bench_module()
     L = {"block": 0, "cand_cap": 128, "waves_per_wg": 1, "grid_wgs": 0, "region": 32, "objs_per_lane": 2,
          "cull_nodes": 0}
-    run = {"workload": "w", "kernel": "k_query_region<32, 2>", "launch": L,
+    run = {"workload": "w", "kernel": "k_query_region<32, 2, 0>", "launch": L,
            "query_source_sha256": b.source_hash(), "hbm_bytes_per_launch": 123.0}
     (tmp_path / "counters_query_w.json").write_text(json.dumps({"runs": [run]}))
     monkeypatch.setattr(b, "COUNTERS_GLOB", str(tmp_path / "counters_query_*.json"))
-    assert b.committed_traffic("w", "k_query_region<32, 2>", dict(L))[0] == 123.0
-    assert b.committed_traffic("w", "k_query_region<32, 2>", {**L, "cull_nodes": 32})[0] is None
-    assert b.committed_traffic("w", "k_query_region<32, 2>", None)[0] is None
-    assert b.committed_traffic("v", "k_query_region<32, 2>", dict(L))[0] is None
+    assert b.committed_traffic("w", "k_query_region<32, 2, 0>", dict(L))[0] == 123.0
+    assert b.committed_traffic("w", "k_query_region<32, 2, 0>", {**L, "cull_nodes": 32})[0] is None
+    assert b.committed_traffic("w", "k_query_region<32, 2, 0>", None)[0] is None
+    assert b.committed_traffic("v", "k_query_region<32, 2, 0>", dict(L))[0] is None
     run["query_source_sha256"] = "0" * 64
     (tmp_path / "counters_query_w.json").write_text(json.dumps(run))
-    assert b.committed_traffic("w", "k_query_region<32, 2>", dict(L))[0] is None
+    assert b.committed_traffic("w", "k_query_region<32, 2, 0>", dict(L))[0] is None
