@@ -933,7 +933,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                                 }
                             }
                         }
-                        if (range_done(ilo, ihi, jlo, jhi)) push = false;
+                        // (a child the accept pass stops at needs no second look)
+                        if (!(accept_pass && (diag2 <= 2.25 * racc2 || cl == 0)) && range_done(ilo, ihi, jlo, jhi))
+                            push = false;
                     }
                     // The accept pass stops at leaves and at nodes whose diagonal
                     // is at most 1.5 racc.  A box's edge accepts light every pixel
