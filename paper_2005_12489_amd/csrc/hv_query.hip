@@ -829,8 +829,12 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
         if (lvl > 0) {
             const int cl = lvl - 1;
             const int64_t ccount = ix.meta[kMaxLevels + cl], coff = ix.meta[cl];
-            // issue all OPL child-box loads first so that they are in flight together
+            // issue all OPL child-box loads first so that they are in flight
+            // together, in the accept pass each with the first vertex of the
+            // child's first object (a node owns a contiguous run of the sorted
+            // objects: node i of level l starts at object i * 16^(l + 1))
             double4 nbk[OPL];
+            double2 repk[OPL];
             uint32_t childk[OPL];
             bool havek[OPL];
 #pragma unroll
@@ -839,12 +843,15 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                 havek[k] = false;
                 childk[k] = 0;
                 nbk[k] = make_double4(0.0, 0.0, 0.0, 0.0);
+                repk[k] = make_double2(0.0, 0.0);
                 if (j < npop) {
                     const int64_t child = (int64_t)(stk[sp - 1 - j] & kIdxMask) * kFan + c;
                     if (child < ccount) {
                         havek[k] = true;
                         childk[k] = (uint32_t)child;
                         nbk[k] = ix.nodes[coff + child];
+                        const int64_t o = child << (4 * lvl);  // lvl = cl + 1
+                        if (accept_pass) repk[k] = reinterpret_cast<const double2 *>(ix.obj)[SEG ? 2 * o : o];
                     }
                 }
             }
@@ -865,6 +872,59 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     // a child whose pixel range is all lit can add nothing:
                     // neither accepts nor objects
                     if (push && range_done(ilo, ihi, jlo, jhi)) push = false;
+                    // Accepts light sample rows in FP32 with the radius ra = r -
+                    // 1e-3 px.  Tile-local coordinates stay below a few hundred px,
+                    // where one FP32 rounding is at most 3e-5 px, so the squared
+                    // distance a claimed sample is known to have is off by less
+                    // than 2 r 1e-4 + r^2 3e-7 px^2 (runs are shrunk by 1e-4 px for
+                    // their own rounding): under a tenth of the room r^2 - ra^2 =
+                    // 2 r 1e-3 - 1e-6 for every r in (1e-3, 64].  No accept claims a
+                    // sample beyond r; samples near an accept's edge fall to the
+                    // exact FP64 test.  For anti-aliased output every accept runs
+                    // on the four sub-sample grids (centres shifted by -+1/4 px in
+                    // x and y) and lights that sub-sample's mask.
+                    const float ra = (float)(r - kAcceptMargin);
+                    const float ra2 = ra * ra;
+                    // lights mask mm's row jj where the sample x (column 0's
+                    // sample at fc0) lies in [lo, hi], within columns [ilo, ihi]
+                    auto light = [&](int mm, int jj, float fc0, float lo, float hi) {
+                        const int a0 = max((int)ceilf(lo - fc0 + 1e-4f), ilo);
+                        const int a1 = min((int)floorf(hi - fc0 - 1e-4f), ihi);
+                        if (a0 > a1) return;
+                        const uint64_t bits = (a1 - a0 == 63 ? ~0ull : ((1ull << (a1 - a0 + 1)) - 1ull)) << a0;
+#pragma unroll
+                        for (int wd = 0; wd < W; ++wd) {
+                            const uint32_t wb = (uint32_t)(bits >> (32 * wd));
+                            if (wb) {
+                                atomicOr(&mask[mm * MW + jj * W + wd], wb);
+                                accepted = true;
+                            }
+                        }
+                    };
+                    if (push && ra > 0.0f && accept_pass) {
+                        // Disk accept (accept pass): the child's first object is an
+                        // object of the index, so every sample within ra of its first
+                        // vertex is lit.  Any node, however large, lights a disk this
+                        // way, so that coarse levels already prune the nodes below.
+                        const double pu = repk[k].x * S - ox, pv = repk[k].y * S - oy;
+                        const float fpu = (float)pu, fpv = (float)pv;
+                        const int r0 = max(jlo, (int)ceil(pv - (double)ra - 0.75 - j0));
+                        const int r1 = min(jhi, (int)floor(pv + (double)ra - 0.25 - j0));
+#pragma unroll
+                        for (int sy = 0; sy < (AA ? 2 : 1); ++sy) {
+                            const float syo = AA ? (sy ? 0.25f : -0.25f) : 0.0f;
+                            for (int jj = r0; jj <= r1; ++jj) {
+                                const float dy = (float)(j0 + (double)jj + 0.5) + syo - fpv;
+                                const float rn = ra2 - dy * dy;
+                                if (rn < 0.0f) continue;
+                                const float h = __builtin_amdgcn_sqrtf(rn);
+#pragma unroll
+                                for (int sx = 0; sx < (AA ? 2 : 1); ++sx)
+                                    light(AA ? 2 * sy + sx : 0, jj, (float)(i0 + 0.5) + (AA ? (sx ? 0.25f : -0.25f) : 0.0f),
+                                          fpu - h, fpu + h);
+                            }
+                        }
+                    }
                     if (push && small) {
                         // Edge accept.  A node box is the exact bounding box of
                         // its objects' coordinates (points, segment endpoints),
@@ -879,20 +939,6 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         //   bx1 - b <= cx <= bx0 + b,            b = sqrt(ra^2 - dyn^2)
                         //     (both ends of the nearer horizontal side),
                         // so the row's accepted pixels are at most three runs.
-                        // The test runs in FP32 with ra = r - 1e-3 px.  Tile-local
-                        // coordinates stay below a few hundred px, where one FP32
-                        // rounding is at most 3e-5 px, so the squared distance a
-                        // claimed centre is known to have is off by less than
-                        // 2 r 1e-4 + r^2 3e-7 px^2 (the runs are shrunk by 1e-4
-                        // px for their own rounding): under a tenth of the room
-                        // r^2 - ra^2 = 2 r 1e-3 - 1e-6 for every r in (1e-3, 64].
-                        // No accept claims a centre beyond r; pixels near an
-                        // accept's edge fall to the exact FP64 test.
-                        // For anti-aliased output the same test runs on each of
-                        // the four sub-sample grids (centres shifted by -+1/4
-                        // px in x and y) and lights that sub-sample's mask.
-                        const float ra = (float)(r - kAcceptMargin);
-                        const float ra2 = ra * ra;
                         const float fx0 = (float)bx0, fx1 = (float)bx1, fy0 = (float)by0, fy1 = (float)by1;
                         // rows of samples: one per pixel row, or two (-+1/4) for
                         // anti-aliased output, each serving its two sub-sample
@@ -913,22 +959,11 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                                 for (int sx = 0; sx < (AA ? 2 : 1); ++sx) {
                                     // sample of region column 0 (exact)
                                     const float fc0 = (float)(i0 + 0.5) + (AA ? (sx ? 0.25f : -0.25f) : 0.0f);
-                                    auto run = [&](float lo, float hi) -> uint64_t {
-                                        const int a0 = max((int)ceilf(lo - fc0 + 1e-4f), ilo);
-                                        const int a1 = min((int)floorf(hi - fc0 - 1e-4f), ihi);
-                                        if (a0 > a1) return 0ull;
-                                        return (a1 - a0 == 63 ? ~0ull : ((1ull << (a1 - a0 + 1)) - 1ull)) << a0;
-                                    };
-                                    uint64_t bits = run(fx1 - b, fx0 + b);
-                                    if (a >= 0.0f) bits |= run(fx0 - a, fx0 + a) | run(fx1 - a, fx1 + a);
                                     const int mm = AA ? 2 * sy + sx : 0;
-#pragma unroll
-                                    for (int wd = 0; wd < W; ++wd) {
-                                        const uint32_t wb = (uint32_t)(bits >> (32 * wd));
-                                        if (wb) {
-                                            atomicOr(&mask[mm * MW + jj * W + wd], wb);
-                                            accepted = true;
-                                        }
+                                    light(mm, jj, fc0, fx1 - b, fx0 + b);
+                                    if (a >= 0.0f) {
+                                        light(mm, jj, fc0, fx0 - a, fx0 + a);
+                                        light(mm, jj, fc0, fx1 - a, fx1 + a);
                                     }
                                 }
                             }
