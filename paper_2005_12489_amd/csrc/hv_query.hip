@@ -885,13 +885,16 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     // x and y) and lights that sub-sample's mask.
                     const float ra = (float)(r - kAcceptMargin);
                     const float ra2 = ra * ra;
-                    // lights mask mm's row jj where the sample x (column 0's
-                    // sample at fc0) lies in [lo, hi], within columns [ilo, ihi]
-                    auto light = [&](int mm, int jj, float fc0, float lo, float hi) {
+                    // the columns of [ilo, ihi] whose sample x (column 0's sample
+                    // at fc0) lies in [lo, hi], as row bits
+                    auto run = [&](float fc0, float lo, float hi) -> uint64_t {
                         const int a0 = max((int)ceilf(lo - fc0 + 1e-4f), ilo);
                         const int a1 = min((int)floorf(hi - fc0 - 1e-4f), ihi);
-                        if (a0 > a1) return;
-                        const uint64_t bits = (a1 - a0 == 63 ? ~0ull : ((1ull << (a1 - a0 + 1)) - 1ull)) << a0;
+                        if (a0 > a1) return 0ull;
+                        return (a1 - a0 == 63 ? ~0ull : ((1ull << (a1 - a0 + 1)) - 1ull)) << a0;
+                    };
+                    // sets row bits in mask mm's row jj (one LDS atomic per word)
+                    auto light = [&](int mm, int jj, uint64_t bits) {
 #pragma unroll
                         for (int wd = 0; wd < W; ++wd) {
                             const uint32_t wb = (uint32_t)(bits >> (32 * wd));
@@ -920,8 +923,8 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                                 const float h = __builtin_amdgcn_sqrtf(rn);
 #pragma unroll
                                 for (int sx = 0; sx < (AA ? 2 : 1); ++sx)
-                                    light(AA ? 2 * sy + sx : 0, jj, (float)(i0 + 0.5) + (AA ? (sx ? 0.25f : -0.25f) : 0.0f),
-                                          fpu - h, fpu + h);
+                                    light(AA ? 2 * sy + sx : 0, jj,
+                                          run((float)(i0 + 0.5) + (AA ? (sx ? 0.25f : -0.25f) : 0.0f), fpu - h, fpu + h));
                             }
                         }
                     }
@@ -959,12 +962,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                                 for (int sx = 0; sx < (AA ? 2 : 1); ++sx) {
                                     // sample of region column 0 (exact)
                                     const float fc0 = (float)(i0 + 0.5) + (AA ? (sx ? 0.25f : -0.25f) : 0.0f);
-                                    const int mm = AA ? 2 * sy + sx : 0;
-                                    light(mm, jj, fc0, fx1 - b, fx0 + b);
-                                    if (a >= 0.0f) {
-                                        light(mm, jj, fc0, fx0 - a, fx0 + a);
-                                        light(mm, jj, fc0, fx1 - a, fx1 + a);
-                                    }
+                                    uint64_t bits = run(fc0, fx1 - b, fx0 + b);
+                                    if (a >= 0.0f) bits |= run(fc0, fx0 - a, fx0 + a) | run(fc0, fx1 - a, fx1 + a);
+                                    light(AA ? 2 * sy + sx : 0, jj, bits);
                                 }
                             }
                         }
