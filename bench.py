@@ -552,7 +552,7 @@ def main():
         torch.cuda.synchronize()
         aa_s = (time.perf_counter() - a0) / 5
         aa = {"tiles_per_s": n / aa_s, "ms_per_call": aa_s * 1e3,
-              "note": "values 0-4 per pixel: the four children one zoom deeper at 2r, 2 x 2 sums"}
+              "note": "values 0-4 per pixel: how many of its four sub-samples (centre -+ 1/4 px in x and y) lie within r, in one pass"}
         del out_aa
         stage(f"anti-aliased: {n / aa_s:.0f} tiles/s")
 

@@ -138,7 +138,9 @@ typedef struct {
                                that side whose queued objects are dealt out over all lanes (block is
                                then unused and cand_cap sizes the queue) */
     int32_t objs_per_lane;  /* region mode: objects each lane loads per leaf step, 1, 2 or 4;
-                               cand_cap must be >= 64 * waves_per_wg * objs_per_lane */
+                               cand_cap must be >= 64 * waves_per_wg; below 64 * waves_per_wg *
+                               objs_per_lane the queue takes a step's objects 64 * waves_per_wg at
+                               a time, draining in between (less LDS: more workgroups per CU) */
     int32_t cull_nodes;     /* cull depth of the per-tile pass: it descends the tree while the next
                                level holds at most this many nodes that meet the tile, 1..256
                                (0 = 256); blocks and regions then walk on from those nodes */
@@ -148,8 +150,8 @@ typedef struct {
  * tests).  Every valid shape produces identical masks.  Extra HV_EINVAL
  * cases: block not 8, 16 or 32, cand_cap < 64 or > 4096, waves_per_wg not 1,
  * 2 or 4, grid_wgs outside [0, 2^20], region not 0, 32 or 64,
- * objs_per_lane not 1, 2 or 4, cand_cap below 64 * waves_per_wg *
- * objs_per_lane in region mode, cull_nodes outside [0, 256], or a shape
+ * objs_per_lane not 1, 2 or 4, cand_cap below 64 * waves_per_wg in region
+ * mode, cull_nodes outside [0, 256], or a shape
  * needing more than 64 KiB of LDS per workgroup. */
 int hv_render_tiles_ex(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
                        const hv_style *style, uint8_t *out_masks, const hv_launch *launch);

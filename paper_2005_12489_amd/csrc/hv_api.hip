@@ -107,8 +107,8 @@ int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s, int64_
     if (s->cull < 1 || s->cull > hv::kFrontier) return fail(HV_EINVAL, "launch.cull_nodes must be in [0, 256]");
     if (s->region != 0 && s->region != 32 && s->region != 64)
         return fail(HV_EINVAL, "launch.region must be 0, 32 or 64");
-    if (s->region && s->cand_cap < 64 * s->waves * s->opl)
-        return fail(HV_EINVAL, "launch.cand_cap must be at least 64 * waves_per_wg * objs_per_lane in region mode");
+    if (s->region && s->cand_cap < 64 * s->waves)
+        return fail(HV_EINVAL, "launch.cand_cap must be at least 64 * waves_per_wg in region mode");
     if (s->block != 8 && s->block != 16 && s->block != 32)
         return fail(HV_EINVAL, "launch.block must be 8, 16 or 32");
     if (s->cand_cap < 64 || s->cand_cap > 4096) return fail(HV_EINVAL, "launch.cand_cap must be in [64, 4096]");
@@ -706,12 +706,15 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     // The default's three shapes come first (queues at their minimum, 64 x
     // waves x objects per lane: larger queues cost occupancy); grid 2^20
     // gives each region its own workgroup, which helps batches whose regions
-    // differ widely in cost.  One wavefront per pixel block (region 0) is
+    // differ widely in cost; a queue of 64 x waves (a leaf step's objects
+    // taken 64 x waves at a time) frees LDS for more workgroups per CU.
+    // One wavefront per pixel block (region 0) is
     // not a candidate: it never won, and without the accept pass a single
     // run of it on a few dense low-zoom tiles can take seconds.
     static const hv_launch cands[] = {
         {0, 128, 1, 0, 32, 2, 0}, {0, 256, 2, 0, 32, 2, 0}, {0, 512, 4, 0, 32, 2, 0}, {0, 128, 1, 0, 32, 2, 128},
         {0, 128, 1, 0, 32, 2, 32}, {0, 512, 4, 0, 32, 2, 32}, {0, 128, 1, 1 << 20, 32, 2, 0},
+        {0, 64, 1, 1 << 20, 32, 2, 0}, {0, 64, 1, 0, 32, 2, 0},
         {0, 64, 1, 0, 32, 1}, {0, 256, 1, 0, 32, 4},
         {0, 128, 2, 0, 32, 1}, {0, 256, 4, 0, 32, 1}, {0, 128, 1, 0, 64, 2}, {0, 256, 2, 0, 64, 2},
         {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2},

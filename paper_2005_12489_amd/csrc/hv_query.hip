@@ -512,10 +512,17 @@ __host__ __device__ inline int region_stack_words(int levels, int threads, int p
     return kFrontier + width * (levels > 0 ? levels : 1);
 }
 
+// The distance query's walk starts from a frontier at level levels - 1 (the
+// root's) at most, so at most levels - 1 levels lie below the frontier.
+__host__ __device__ inline int query_stack_words(int levels, int threads, int per_lane) {
+    const int width = threads * per_lane < kInnerWidth ? threads * per_lane : kInnerWidth;
+    return kFrontier + width * (levels > 1 ? levels - 1 : 0);
+}
+
 // stack | queued objects (SoA) | cell prefix sums | mask rows (four sets for
 // anti-aliased output, one per sub-sample) | control | scan scratch
 __host__ __device__ inline size_t region_lds_bytes(int cap, int levels, int threads, int rs, int opl, int aa = 0) {
-    return align16((size_t)region_stack_words(levels, threads, opl) * 4) + align16((size_t)cap * kCandBytes) +
+    return align16((size_t)query_stack_words(levels, threads, opl) * 4) + align16((size_t)cap * kCandBytes) +
            align16((size_t)(cap + 1) * 4) + align16((size_t)rs * (rs / 32) * 4 * (aa ? 4 : 1)) + 16 + 64;
 }
 
@@ -1014,6 +1021,15 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < OPL; ++k) {
+                // a queue smaller than a step's OPL * threads objects takes
+                // them threads at a time, draining in between
+                if (k > 0 && cap < nthr * OPL) {
+                    __syncthreads();
+                    if (ctl[1] > cap - nthr && drain()) {
+                        done = true;
+                        break;
+                    }
+                }
                 const double ax = ob[k].x, ay = ob[k].y, bxx = ob[k].z, byy = ob[k].w;
                 bool keep = false;
                 double ua = 0, va = 0, ub = 0, vb = 0;
@@ -1048,6 +1064,7 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                 }
             }
         }
+        if (done) break;
         if (__syncthreads_or(accepted)) {
             // accepts may have lit the whole region
             bool full = true;
@@ -1057,7 +1074,8 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                 break;
             }
         }
-        if (ctl[1] > cap - nthr * OPL && drain()) {
+        // room for what the next leaf step queues at once
+        if (ctl[1] > cap - (cap >= nthr * OPL ? nthr * OPL : nthr) && drain()) {
             done = true;
             break;
         }
@@ -1095,7 +1113,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     unsigned char *base = reinterpret_cast<unsigned char *>(smem);
     RegionLds L;
     L.stk = reinterpret_cast<uint32_t *>(base);
-    unsigned char *cb = base + align16((size_t)region_stack_words(max_levels, blockDim.x, OPL) * 4);
+    unsigned char *cb = base + align16((size_t)query_stack_words(max_levels, blockDim.x, OPL) * 4);
     L.ca = reinterpret_cast<double2 *>(cb);
     L.cd = L.ca + cap;
     L.ci = reinterpret_cast<double *>(L.cd + cap);

@@ -16,7 +16,8 @@ brute force of N_box and N_unlit_cand).  Per-zoom sums are kept beside the
 totals.
 
 Calls only the oracle and the seeded generators.  Usage:
-    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4]
+    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4] [c3]
+(c3: sampled and extrapolated per zoom, see c3_sampled).
 """
 from __future__ import annotations
 
@@ -30,6 +31,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
+sys.path.insert(0, HERE)
+sys.path.insert(0, os.path.dirname(HERE))
 
 import hvgen  # noqa: E402
 import oracle  # noqa: E402
@@ -53,8 +56,76 @@ def workload(key):
     raise KeyError(key)
 
 
+def c3_sampled(data):
+    """The 1e9 points cannot be indexed whole on the host.  Their work is
+    counted on the zoom-stratified sample of tests/golden/fullsize_c3.npz (27
+    requests per zoom at zooms 3-18, each tile against an oracle index over
+    the points near it, as make_fullsize_parity.py does) and extrapolated per
+    zoom to every request of the 10,000 at those zooms: the mean per sampled
+    tile of a zoom times the number of requests at that zoom."""
+    import make_fullsize_parity as mfp
+    from helpers import stratified_sample
+    name = "points-1e9-clustered-10000tiles-z0-18-r1-3"
+    n = 1_000_000_000
+    tiles, r = hvgen.c3_requests(10_000)
+    idx = stratified_sample(tiles, mfp.PER_ZOOM, mfp.SEED, zmin=mfp.ZMIN_C3)
+    pts = hvgen.gen_c3_points(n)
+    cells = np.empty(n, dtype=np.uint16)
+    for s in range(0, n, 10_000_000):
+        cells[s:s + 10_000_000] = mfp._cell_of(pts[s:s + 10_000_000])
+    start = np.zeros(65537, dtype=np.int64)
+    start[1:] = np.cumsum(np.bincount(cells, minlength=65536))
+    order = np.argsort(cells, kind="stable")
+    del cells
+    pts = pts[order]
+    del order
+    cnt = np.zeros((len(idx), 5), dtype=np.int64)
+    t0 = time.time()
+    for k, t in enumerate(idx):
+        z, x, y = (int(v) for v in tiles[t])
+        if z >= 8:
+            x0 = x1 = x >> (z - 8)
+            y0 = y1 = y >> (z - 8)
+        else:
+            x0, x1 = x << (8 - z), ((x + 1) << (8 - z)) - 1
+            y0, y1 = y << (8 - z), ((y + 1) << (8 - z)) - 1
+        xa, xb = max(0, x0 - 1), min(255, x1 + 1)
+        sub = np.concatenate([pts[start[cy * 256 + xa]:start[cy * 256 + xb + 1]]
+                              for cy in range(max(0, y0 - 1), min(255, y1 + 1) + 1)])
+        if len(sub):
+            cnt[k] = oracle.OracleIndex(sub, oracle.POINTS).render(tiles[t:t + 1], r[t:t + 1], want_bit=False,
+                                                                   want_counters=True)["counters"][0]
+        if k % 20 == 0:
+            print(f"{name}: sampled tile {k + 1}/{len(idx)} z{z}, {time.time() - t0:.0f}s", flush=True)
+    zooms, tot_b, tot_f, tot_n = {}, 0.0, 0.0, 0
+    for z in np.unique(tiles[idx, 0]):
+        sel = tiles[idx, 0] == z
+        n_z = int((tiles[:, 0] == z).sum())
+        cz = cnt[sel].mean(0)
+        b = 8192 + 16 * cz[oracle.C_UNLIT_CAND]
+        f = 6 * (cz[oracle.C_NBOX_UNLIT] + cz[oracle.C_LIT])
+        zooms[str(int(z))] = {"sampled_tiles": int(sel.sum()), "requests": n_z, "bytes_per_tile": float(b),
+                              "flops_per_tile": float(f)}
+        tot_b += n_z * b
+        tot_f += n_z * f
+        tot_n += n_z
+    data[name + "/zooms-3-18-extrapolated"] = {
+        "tiles": tot_n, "objects": n, "alg_bytes": int(round(tot_b)), "alg_flops": int(round(tot_f)),
+        "bytes_per_tile": tot_b / tot_n, "per_zoom": zooms, "extrapolated": True,
+        "note": "counted by the oracle on 27 sampled requests per zoom at zooms 3-18 and extrapolated per zoom to "
+                "the requests of the 10,000 at those zooms (zooms 0-2 are not covered); bytes = 8192 per mask + "
+                "16 per point needed to certify an unlit pixel; flops = 6 per (unlit pixel, box-meeting point) "
+                "pair + one witness test per lit pixel"}
+    print(name, {k: v for k, v in data[name + "/zooms-3-18-extrapolated"].items() if k != "per_zoom"}, flush=True)
+
+
 def main(keys):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    if "c3" in keys:
+        keys = [k for k in keys if k != "c3"]
+        c3_sampled(data)
+        with open(OUT, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
     for key in keys:
         t0 = time.time()
         name, objs, kind, tiles, r = workload(key)

@@ -78,7 +78,7 @@ def test_render_rejects_host_output_and_bad_shapes(hv):
         for bad in (dict(block=12), dict(cand_cap=32), dict(cand_cap=5000), dict(waves_per_wg=3),
                     dict(waves_per_wg=8), dict(grid_wgs=-1), dict(grid_wgs=1 << 21), dict(region=16),
                     dict(region=64, waves_per_wg=4, cand_cap=128), dict(region=32, objs_per_lane=3),
-                    dict(region=32, objs_per_lane=4, cand_cap=128), dict(cull_nodes=257),
+                    dict(region=32, waves_per_wg=2, objs_per_lane=4, cand_cap=64), dict(cull_nodes=257),
                     dict(cull_nodes=-1)):
             with pytest.raises(hv.HvError, match="launch"):
                 hv.hv_render_tiles_ex(h, [(3, 1, 1)], 1.0, buf.ctypes.data, bad)

@@ -68,6 +68,7 @@ def test_aa_points_c1_all_tiles(hv, torch):
     check_aa(got, ix.render_aa(tiles, r), "aa c1", paper=ix.render_aa(tiles, r, mode="paper"))
     for L in (dict(region=64, waves_per_wg=4, cand_cap=256), dict(region=0, block=16, waves_per_wg=2),
               dict(region=32, waves_per_wg=1, objs_per_lane=2, cand_cap=128),
+              dict(region=32, waves_per_wg=1, objs_per_lane=2, cand_cap=64, grid_wgs=1 << 20),
               dict(region=32, waves_per_wg=2, objs_per_lane=4, cand_cap=512, grid_wgs=7)):
         assert np.array_equal(render_aa(hv, torch, h, tiles, r, launch=L), got), L
     hv.hv_free(h)

@@ -106,6 +106,10 @@ SHAPES += [dict(region=rs, cand_cap=64 * w * o, waves_per_wg=w, objs_per_lane=o)
            for rs in (32, 64) for w in (1, 2, 4) for o in (1, 2, 4)]
 SHAPES += [dict(region=rs, cand_cap=512, waves_per_wg=w, objs_per_lane=o, grid_wgs=7)
            for rs in (32, 64) for w, o in ((1, 1), (2, 4))]
+# queues below a leaf step's objects: they take them 64 * waves at a time
+SHAPES += [dict(region=rs, cand_cap=c * w, waves_per_wg=w, objs_per_lane=o, grid_wgs=g)
+           for rs, c, w, o, g in ((32, 64, 1, 2, 0), (32, 64, 1, 2, 1 << 20), (32, 96, 1, 2, 0), (32, 64, 2, 4, 0),
+                                  (32, 160, 1, 4, 7), (64, 64, 4, 2, 0))]
 # cull depth: from the root alone to a deep frontier
 SHAPES += [dict(region=32, cand_cap=128, waves_per_wg=1, objs_per_lane=2, cull_nodes=c) for c in (1, 3, 16, 64, 255)]
 SHAPES += [dict(block=16, cand_cap=64, waves_per_wg=2, cull_nodes=c) for c in (1, 40)]
@@ -113,7 +117,8 @@ SHAPES += [dict(block=16, cand_cap=64, waves_per_wg=2, cull_nodes=c) for c in (1
 
 def test_launch_shapes_identical(hv, torch):
     """Every launch shape (block size, LDS candidate capacity -- 64 forces a
-    flush after every leaf step --, waves per workgroup, persistent grid
+    flush after every leaf step, less than a step's objects flushes within
+    it --, waves per workgroup, persistent grid
     size, including a 7-workgroup grid that makes each wave loop over many
     blocks, and the cull depth of the per-tile pass) gives bit-identical
     masks."""
