@@ -145,15 +145,43 @@ def committed_traffic(workload: str, kernel: str, launch):
     return None, None
 
 
-def roofline_record(workload: str, launch, frontier_ms: float, query_ms: float):
+def algorithmic_work(workload: str, zooms=None):
+    """Algorithmic bytes and flops of one launch of a workload from the
+    oracle's counters (tests/golden/algorithmic_work.json).  A workload too
+    large for the oracle to count whole has an entry counted on a per-zoom
+    sample and extrapolated per zoom ("<workload>/zooms-A-B-extrapolated");
+    its requests at zooms the entry does not cover (`zooms`: the zoom of each
+    request) add their 8192 mask bytes and nothing else, so the figure is a
+    lower bound, and the record says so."""
+    if not os.path.exists(WORK_FILE):
+        return None
+    data = json.load(open(WORK_FILE))
+    if workload in data:
+        return dict(data[workload])
+    keys = [k for k in data if k.startswith(workload + "/zooms-") and data[k].get("extrapolated")]
+    if not keys or zooms is None:
+        return None
+    e = data[keys[0]]
+    zs = np.asarray(zooms)
+    covered = np.isin(zs, [int(z) for z in e["per_zoom"]])
+    assert int(covered.sum()) == e["tiles"], "extrapolated counts do not match this batch's zoom mix"
+    rest = int((~covered).sum())
+    return {"alg_bytes": e["alg_bytes"] + 8192 * rest, "alg_flops": e["alg_flops"],
+            "extrapolated": f"{keys[0]}: {e['tiles']} requests at zooms {min(map(int, e['per_zoom']))}-"
+                            f"{max(map(int, e['per_zoom']))} extrapolated per zoom from the oracle's counts on a "
+                            f"sample of them; the {rest} other requests count their mask bytes only (a lower "
+                            f"bound, so achieved and frac are lower bounds)"}
+
+
+def roofline_record(workload: str, launch, frontier_ms: float, query_ms: float, zooms=None):
     """The query kernel against its roofline.  Algorithmic work per launch
-    comes from the oracle's counters (tests/golden/algorithmic_work.json):
-    bytes = masks + the objects unlit pixels need, flops = the exact
-    distance tests those pixels need plus one witness per lit pixel.  The
-    roofline time is max(bytes / 8 TB/s, flops / 78.6 TFLOP/s); the larger
-    term names the bound ("hbm" or "alu": FP64 vector arithmetic), and the
-    other side is reported beside it."""
-    work = json.load(open(WORK_FILE)).get(workload) if os.path.exists(WORK_FILE) else None
+    comes from the oracle's counters (algorithmic_work): bytes = masks + the
+    objects unlit pixels need, flops = the exact distance tests those pixels
+    need plus one witness per lit pixel.  The roofline time is max(bytes /
+    8 TB/s, flops / 78.6 TFLOP/s); the larger term names the bound ("hbm" or
+    "alu": FP64 vector arithmetic), and the other side is reported beside
+    it."""
+    work = algorithmic_work(workload, zooms)
     if not work:
         return None
     kname = query_kernel_name(launch)
@@ -167,6 +195,8 @@ def roofline_record(workload: str, launch, frontier_ms: float, query_ms: float):
            "alg_bytes_per_launch": work["alg_bytes"], "alg_flops_per_launch": work["alg_flops"],
            "roofline_ms": max(t_bytes, t_flops) * 1e3, "traffic": traffic, "traffic_source": src,
            "traffic_gbs": traffic / sec / 1e9 if traffic else None}
+    if work.get("extrapolated"):
+        rec["alg_extrapolated"] = work["extrapolated"]
     if t_flops > t_bytes:
         rec.update({"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": tfl / FP64_PEAK_TFLOPS, "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS})
@@ -575,7 +605,7 @@ def main():
         lat = [a.elapsed_time(b) for a, b in pe]
         per_tile = {"tiles_per_s": m / (q1 - q0), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "launches": m}
 
-    roofline = roofline_record(wl["name"], launch, frontier_ms, query_ms)
+    roofline = roofline_record(wl["name"], launch, frontier_ms, query_ms, zooms=tiles[:, 0])
 
     cpu = None
     if not args.no_cpu_baseline:

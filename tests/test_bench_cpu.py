@@ -5,6 +5,9 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -51,6 +54,26 @@ def test_roofline_bound_is_the_slower_roof(tmp_path, monkeypatch):
     assert abs(r["achieved"] - 0.0786) < 1e-12 and abs(r["frac"] - 0.001) < 1e-12
     assert list(r)[:6] == ["bound", "achieved", "peak", "unit", "frac", "traffic"]
     assert b.roofline_record("absent", None, 0.1, 1.0) is None
+
+
+def test_roofline_from_extrapolated_counts(tmp_path, monkeypatch):
+    """A workload counted on a per-zoom sample: requests at the covered zooms
+    take the extrapolated figures, the others their mask bytes only, and the
+    record says the figure is a lower bound."""
+    import json
+    b = _bench_module()
+    work = {"w/zooms-3-4-extrapolated": {"alg_bytes": 1_000_000, "alg_flops": 78_600_000_000, "tiles": 3,
+                                          "extrapolated": True, "per_zoom": {"3": {}, "4": {}}}}
+    f = tmp_path / "work.json"
+    f.write_text(json.dumps(work))
+    monkeypatch.setattr(b, "WORK_FILE", str(f))
+    monkeypatch.setattr(b, "COUNTERS_GLOB", str(tmp_path / "none_*.json"))
+    r = b.roofline_record("w", None, 0.1, 1000.0, zooms=np.array([0, 3, 3, 4, 1]))
+    assert r["alg_bytes_per_launch"] == 1_000_000 + 2 * 8192 and r["alg_flops_per_launch"] == 78_600_000_000
+    assert r["bound"] == "alu" and abs(r["frac"] - 0.001) < 1e-12 and "lower bound" in r["alg_extrapolated"]
+    assert b.roofline_record("w", None, 0.1, 1.0) is None          # zoom mix unknown
+    with pytest.raises(AssertionError):
+        b.roofline_record("w", None, 0.1, 1.0, zooms=np.array([3, 4]))   # another batch
 
 
 def test_counters_are_matched_on_the_full_launch(tmp_path, monkeypatch):
