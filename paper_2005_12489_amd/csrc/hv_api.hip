@@ -46,6 +46,7 @@ hv::DevIndex dev_view(const hv_index *ix) {
     hv::DevIndex d;
     d.obj = ix->a.obj;
     d.nodes = ix->a.nodes;
+    d.rep = ix->a.rep;
     d.meta = ix->a.meta;
     d.n = ix->a.n;
     d.levels = ix->a.levels;

@@ -370,6 +370,18 @@ __global__ __launch_bounds__(256) void k_level_boxes(const double4 *__restrict__
     parent[i] = make_double4(x0, y0, x1, y1);
 }
 
+// Node i of level l owns the sorted objects [i * 16^(l + 1), (i + 1) *
+// 16^(l + 1)); its representative is the first vertex of the first of them,
+// a point of an object inside the node's box.
+template <int W>
+__global__ __launch_bounds__(256) void k_node_reps(const double *__restrict__ obj, int shift,
+                                                   double2 *__restrict__ rep, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t o = i << shift;
+    rep[i] = make_double2(obj[o * W], obj[o * W + 1]);
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Bits per axis of the Hilbert grid: enough for ~16 cells per object on
@@ -507,10 +519,12 @@ BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first,
 void free_index_arrays(IndexArrays *a) {
     if (a->obj) (void)hipFree(a->obj);
     if (a->nodes) (void)hipFree(a->nodes);
+    if (a->rep) (void)hipFree(a->rep);
     if (a->order) (void)hipFree(a->order);
     if (a->meta) (void)hipFree(a->meta);
     a->obj = nullptr;
     a->nodes = nullptr;
+    a->rep = nullptr;
     a->order = nullptr;
     a->meta = nullptr;
 }
@@ -576,8 +590,10 @@ BuildResult build_index(const double *objects, int kind_flags, int64_t n, hipStr
     HV_TRY(hipMalloc((void **)&out->obj, sizeof(double) * W * n));
     HV_TRY(hipMalloc((void **)&out->order, sizeof(uint32_t) * n));
     HV_TRY(hipMalloc((void **)&out->nodes, sizeof(double4) * total));
+    HV_TRY(hipMalloc((void **)&out->rep, sizeof(double2) * total));
     v0 = out->order;  // the sort's value buffer doubles as the stored order
-    out->device_bytes = (int64_t)(sizeof(double) * W * n + sizeof(uint32_t) * n + sizeof(double4) * total);
+    out->device_bytes = (int64_t)(sizeof(double) * W * n + sizeof(uint32_t) * n +
+                                  (sizeof(double4) + sizeof(double2)) * total);
 
     {
         int64_t meta[2 * kMaxLevels] = {};
@@ -625,6 +641,15 @@ BuildResult build_index(const double *objects, int kind_flags, int64_t n, hipStr
         const int64_t np = out->level_cnt[l];
         hipLaunchKernelGGL(k_level_boxes, dim3((uint32_t)cdiv(np, 256)), dim3(256), 0, st,
                            out->nodes + out->level_off[l - 1], out->level_cnt[l - 1], out->nodes + out->level_off[l], np);
+    }
+    for (int l = 0; l < levels; ++l) {
+        const int64_t np = out->level_cnt[l];
+        if (seg)
+            hipLaunchKernelGGL(k_node_reps<4>, dim3((uint32_t)cdiv(np, 256)), dim3(256), 0, st, out->obj, 4 * (l + 1),
+                               out->rep + out->level_off[l], np);
+        else
+            hipLaunchKernelGGL(k_node_reps<2>, dim3((uint32_t)cdiv(np, 256)), dim3(256), 0, st, out->obj, 4 * (l + 1),
+                               out->rep + out->level_off[l], np);
     }
     HV_TRY(hipGetLastError());
     int herr = 0;

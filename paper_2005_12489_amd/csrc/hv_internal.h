@@ -22,6 +22,7 @@ constexpr double kCullPad = 1e-5;  // px beyond r for every cull box
 struct DevIndex {
     const double *obj;           // Hilbert order; 2 (points) or 4 (segments) doubles each
     const double4 *nodes;        // all levels, level 0 (leaves) first; (minX, minY, maxX, maxY)
+    const double2 *rep;          // per node, same order: the first vertex of its first object
     const int64_t *meta;         // [0, kMaxLevels): level offsets; [kMaxLevels, 2*kMaxLevels): counts
     int64_t n;
     int32_t levels;
@@ -51,6 +52,7 @@ struct BuildResult {
 struct IndexArrays {
     double *obj = nullptr;
     double4 *nodes = nullptr;
+    double2 *rep = nullptr;      // per node: the first vertex of its first object
     uint32_t *order = nullptr;
     int64_t *meta = nullptr;     // device copy of level_off / level_cnt
     int64_t n = 0;

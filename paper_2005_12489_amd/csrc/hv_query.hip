@@ -837,9 +837,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
             const int cl = lvl - 1;
             const int64_t ccount = ix.meta[kMaxLevels + cl], coff = ix.meta[cl];
             // issue all OPL child-box loads first so that they are in flight
-            // together, in the accept pass each with the first vertex of the
-            // child's first object (a node owns a contiguous run of the sorted
-            // objects: node i of level l starts at object i * 16^(l + 1))
+            // together, in the accept pass each with the child's
+            // representative (the first vertex of its first object), stored
+            // beside the boxes so that a node's children read it contiguously
             double4 nbk[OPL];
             double2 repk[OPL];
             uint32_t childk[OPL];
@@ -857,8 +857,7 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         havek[k] = true;
                         childk[k] = (uint32_t)child;
                         nbk[k] = ix.nodes[coff + child];
-                        const int64_t o = child << (4 * lvl);  // lvl = cl + 1
-                        if (accept_pass) repk[k] = reinterpret_cast<const double2 *>(ix.obj)[SEG ? 2 * o : o];
+                        if (accept_pass) repk[k] = ix.rep[coff + child];
                     }
                 }
             }
@@ -912,9 +911,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         }
                     };
                     if (push && ra > 0.0f && accept_pass) {
-                        // Disk accept (accept pass): the child's first object is an
-                        // object of the index, so every sample within ra of its first
-                        // vertex is lit.  Any node, however large, lights a disk this
+                        // Disk accept (accept pass): the child's representative is a
+                        // vertex of an object of the index, so every sample within ra
+                        // of it is lit.  Any node, however large, lights a disk this
                         // way, so that coarse levels already prune the nodes below.
                         const double pu = repk[k].x * S - ox, pv = repk[k].y * S - oy;
                         const float fpu = (float)pu, fpv = (float)pv;
