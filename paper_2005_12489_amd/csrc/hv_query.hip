@@ -891,6 +891,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     // x and y) and lights that sub-sample's mask.
                     const float ra = (float)(r - kAcceptMargin);
                     const float ra2 = ra * ra;
+                    // with one mask word per row: the child's columns as row
+                    // bits, so that rows already lit there are skipped
+                    const uint32_t rowwant = (uint32_t)(((2ull << (ihi - ilo)) - 1ull) << ilo);
                     // the columns of [ilo, ihi] whose sample x (column 0's sample
                     // at fc0) lies in [lo, hi], as row bits
                     auto run = [&](float fc0, float lo, float hi) -> uint64_t {
@@ -923,6 +926,7 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         for (int sy = 0; sy < (AA ? 2 : 1); ++sy) {
                             const float syo = AA ? (sy ? 0.25f : -0.25f) : 0.0f;
                             for (int jj = r0; jj <= r1; ++jj) {
+                                if (!AA && W == 1 && (mask[jj] & rowwant) == rowwant) continue;
                                 const float dy = (float)(j0 + (double)jj + 0.5) + syo - fpv;
                                 const float rn = ra2 - dy * dy;
                                 if (rn < 0.0f) continue;
@@ -956,6 +960,7 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         for (int sy = 0; sy < (AA ? 2 : 1); ++sy) {
                             const float syo = AA ? (sy ? 0.25f : -0.25f) : 0.0f;
                             for (int jj = jlo; jj <= jhi && ra > 0.0f; ++jj) {
+                                if (!AA && W == 1 && (mask[jj] & rowwant) == rowwant) continue;
                                 const float cy = (float)(j0 + (double)jj + 0.5) + syo;  // exact
                                 const float ey0 = fabsf(cy - fy0), ey1 = fabsf(cy - fy1);
                                 const float dyn = fminf(ey0, ey1), dyf = fmaxf(ey0, ey1);
