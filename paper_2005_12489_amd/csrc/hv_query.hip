@@ -892,7 +892,8 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                     const float ra = (float)(r - kAcceptMargin);
                     const float ra2 = ra * ra;
                     // with one mask word per row: the child's columns as row
-                    // bits, so that rows already lit there are skipped
+                    // bits, so that rows already lit there (in both masks a
+                    // sample row serves, for anti-aliased output) are skipped
                     const uint32_t rowwant = (uint32_t)(((2ull << (ihi - ilo)) - 1ull) << ilo);
                     // the columns of [ilo, ihi] whose sample x (column 0's sample
                     // at fc0) lies in [lo, hi], as row bits
@@ -926,7 +927,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         for (int sy = 0; sy < (AA ? 2 : 1); ++sy) {
                             const float syo = AA ? (sy ? 0.25f : -0.25f) : 0.0f;
                             for (int jj = r0; jj <= r1; ++jj) {
-                                if (!AA && W == 1 && (mask[jj] & rowwant) == rowwant) continue;
+                                if (W == 1 && (mask[(AA ? 2 * sy : 0) * MW + jj] & rowwant) == rowwant &&
+                                    (!AA || (mask[(2 * sy + 1) * MW + jj] & rowwant) == rowwant))
+                                    continue;
                                 const float dy = (float)(j0 + (double)jj + 0.5) + syo - fpv;
                                 const float rn = ra2 - dy * dy;
                                 if (rn < 0.0f) continue;
@@ -960,7 +963,9 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         for (int sy = 0; sy < (AA ? 2 : 1); ++sy) {
                             const float syo = AA ? (sy ? 0.25f : -0.25f) : 0.0f;
                             for (int jj = jlo; jj <= jhi && ra > 0.0f; ++jj) {
-                                if (!AA && W == 1 && (mask[jj] & rowwant) == rowwant) continue;
+                                if (W == 1 && (mask[(AA ? 2 * sy : 0) * MW + jj] & rowwant) == rowwant &&
+                                    (!AA || (mask[(2 * sy + 1) * MW + jj] & rowwant) == rowwant))
+                                    continue;
                                 const float cy = (float)(j0 + (double)jj + 0.5) + syo;  // exact
                                 const float ey0 = fabsf(cy - fy0), ey1 = fabsf(cy - fy1);
                                 const float dyn = fminf(ey0, ey1), dyf = fmaxf(ey0, ey1);
@@ -1062,7 +1067,13 @@ __device__ __forceinline__ void region_query(const DevIndex &ix, const DevReq &r
                         const double dx = ub - ua, dy = vb - va;
                         const double l2 = dx * dx + dy * dy;
                         L.cd[slot] = make_double2(dx, dy);
-                        L.ci[slot] = l2 > 0.0 ? 1.0 / l2 : 0.0;
+                        // 1 / l2: the hardware reciprocal and two Newton steps
+                        // (each doubles its correct bits), within an ulp or so
+                        // of the quotient at a fraction of a division's cost
+                        double iv = __builtin_amdgcn_rcp(l2);
+                        iv = fma(iv, fma(-l2, iv, 1.0), iv);
+                        iv = fma(iv, fma(-l2, iv, 1.0), iv);
+                        L.ci[slot] = l2 > 0.0 ? iv : 0.0;
                     }
                     L.crng[slot] = rg;
                 }
