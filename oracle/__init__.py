@@ -66,6 +66,8 @@ def _bind(lib):
     lib.oracle_free_polygons.argtypes = [P]
     lib.oracle_render_fill.restype = ctypes.c_int
     lib.oracle_render_fill.argtypes = [P, P, I64, P, P, ctypes.c_int]
+    lib.oracle_fill_counters.restype = ctypes.c_int
+    lib.oracle_fill_counters.argtypes = [P, P, I64, P, ctypes.c_int]
     lib.oracle_render_aa.restype = ctypes.c_int
     lib.oracle_render_aa.argtypes = [P, P, I64, P, ctypes.c_int, P, P, P, ctypes.c_int]
     return lib
@@ -204,3 +206,16 @@ class OraclePolygons:
         if self._lib.oracle_render_fill(self._h, _ptr(t), n, _ptr(tri), _ptr(bit), th) != 0:
             raise ValueError("oracle_render_fill rejected its arguments")
         return {"tri": tri, "bit": bit}
+
+    def counters(self, tiles, nthreads: int | None = None):
+        """Work of filling each tile, (n, 4) int64: candidate polygons (boxes
+        holding a pixel centre), needed edges (edges of those polygons that
+        a ray on one of the polygon's centre rows crosses in y), (edge, row)
+        crossings, and (pixel, candidate polygon) pairs."""
+        t = np.ascontiguousarray(tiles, dtype=np.int32).reshape(-1, 3)
+        n = t.shape[0]
+        cnt = np.zeros((n, 4), dtype=np.int64)
+        th = default_threads() if nthreads is None else nthreads
+        if self._lib.oracle_fill_counters(self._h, _ptr(t), n, _ptr(cnt), th) != 0:
+            raise ValueError("oracle_fill_counters rejected its arguments")
+        return cnt

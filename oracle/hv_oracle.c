@@ -841,6 +841,116 @@ static void *worker_fill(void *arg)
     return NULL;
 }
 
+/*
+ * Work counters of filling one tile, for the fill roofline.  Algorithm 2
+ * decides a pixel by the parity of a polygon's edges crossed by a ray from
+ * the pixel centre along its row, for each polygon whose box holds the
+ * centre.  Per tile:
+ *   cnt[0]  candidate polygons: boxes that hold at least one pixel centre;
+ *   cnt[1]  needed edges: edges of candidate polygons that a ray on one of
+ *           the polygon's centre rows crosses in y (the half-open rule of
+ *           the fill above: exactly one end strictly below the row), the
+ *           edges whose crossings decide some parity;
+ *   cnt[2]  (edge, row) crossings: over those edges, the rows counted;
+ *   cnt[3]  (pixel, candidate polygon) pairs: the centres each candidate
+ *           polygon's box holds.
+ * Algorithmic bytes = 8192 + 32 cnt[1]; flops = 5 cnt[2] (the crossing's x:
+ * two differences, a product, a quotient and a sum) + cnt[3] (one parity
+ * test per pair).
+ */
+static void fill_counters_tile(const or_poly *P, int z, int64_t tx, int64_t ty, int64_t *cnt, int64_t *stack)
+{
+    const double S = ldexp(256.0, z);
+    const double ox = (double)tx * 256.0, oy = (double)ty * 256.0;
+    const or_index *M = P->mbr;
+    /* the tile's pixel centres span [0.5, 255.5] in tile-local px */
+    const obox q = { (ox + 0.5) / S, (oy + 0.5) / S, (ox + 255.5) / S, (oy + 255.5) / S };
+    int64_t cand = 0, need = 0, pairs = 0, px = 0;
+    int64_t sp = 0;
+    if (M->root >= 0) stack[sp++] = M->root;
+    while (sp > 0) {
+        const int64_t nd = stack[--sp];
+        if (!box_meets(&M->box[nd], &q)) continue;
+        const int64_t *ch = M->child + M->first[nd];
+        if (!M->leaf[nd]) {
+            for (int32_t c = 0; c < M->count[nd]; ++c) stack[sp++] = ch[c];
+            continue;
+        }
+        for (int32_t c = 0; c < M->count[nd]; ++c) {
+            const int64_t p = ch[c];
+            const obox b = obj_box(M, p);
+            /* centres i + 0.5 inside [bx0, bx1], rows likewise */
+            const double bx0 = b.x0 * S - ox, bx1 = b.x1 * S - ox, by0 = b.y0 * S - oy, by1 = b.y1 * S - oy;
+            const double fi0 = fmax(ceil(bx0 - 0.5), 0.0), fi1 = fmin(floor(bx1 - 0.5), 255.0);
+            const double fj0 = fmax(ceil(by0 - 0.5), 0.0), fj1 = fmin(floor(by1 - 0.5), 255.0);
+            if (fi0 > fi1 || fj0 > fj1) continue;
+            ++cand;
+            px += (int64_t)(fi1 - fi0 + 1.0) * (int64_t)(fj1 - fj0 + 1.0);
+            for (int64_t e = P->first[p]; e < P->first[p + 1]; ++e) {
+                const double ay = P->ay[e] * S - oy, by = P->by[e] * S - oy;
+                if (ay == by) continue;
+                const double lo = fmin(ay, by), hi = fmax(ay, by);
+                /* rows j with lo <= j + 0.5 < hi */
+                const double rj0 = fmax(ceil(lo - 0.5), fj0), rj1 = fmin(ceil(hi - 0.5) - 1.0, fj1);
+                if (rj0 > rj1) continue;
+                ++need;
+                pairs += (int64_t)(rj1 - rj0 + 1.0);
+            }
+        }
+    }
+    cnt[0] = cand;
+    cnt[1] = need;
+    cnt[2] = pairs;
+    cnt[3] = px;
+}
+
+typedef struct {
+    const or_poly *P;
+    const int32_t *tiles;
+    int64_t ntiles;
+    int64_t *cnt;
+    int64_t next;
+    int err;
+} job_fillcnt;
+
+static void *worker_fillcnt(void *arg)
+{
+    job_fillcnt *jb = (job_fillcnt *)arg;
+    int64_t *stack = malloc(sizeof(int64_t) * (size_t)OR_FANOUT * (size_t)(jb->P->mbr->depth + 2));
+    if (!stack) { __atomic_store_n(&jb->err, 1, __ATOMIC_RELAXED); return NULL; }
+    for (;;) {
+        int64_t t = __atomic_fetch_add(&jb->next, 1, __ATOMIC_RELAXED);
+        if (t >= jb->ntiles) break;
+        const int32_t *tl = jb->tiles + 3 * t;
+        fill_counters_tile(jb->P, tl[0], tl[1], tl[2], jb->cnt + 4 * t, stack);
+    }
+    free(stack);
+    return NULL;
+}
+
+/* Fill work counters (see fill_counters_tile): cnt is ntiles x 4.
+ * Returns 0, or -1 on a bad argument. */
+int oracle_fill_counters(const void *h, const int32_t *tiles, int64_t ntiles, int64_t *cnt, int nthreads)
+{
+    const or_poly *P = (const or_poly *)h;
+    if (!P || ntiles < 0 || (ntiles > 0 && (!tiles || !cnt))) return -1;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int32_t z = tiles[3 * t], x = tiles[3 * t + 1], y = tiles[3 * t + 2];
+        if (z < 0 || z > 30 || x < 0 || y < 0 || (int64_t)x >= ((int64_t)1 << z) || (int64_t)y >= ((int64_t)1 << z))
+            return -1;
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    job_fillcnt jb = { P, tiles, ntiles, cnt, 0, 0 };
+    pthread_t th[256];
+    int started = 0;
+    for (int k = 1; k < nthreads; ++k)
+        if (pthread_create(&th[started], NULL, worker_fillcnt, &jb) == 0) ++started;
+    worker_fillcnt(&jb);
+    for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
+    return jb.err ? -1 : 0;
+}
+
 /* Fill masks of polygons (see above).  tiles as for oracle_render; tri
  * (required) and bit (optional) are ntiles x 65536 bytes, row-major from
  * the north-west pixel.  Returns 0, or -1 on a bad argument. */

@@ -616,6 +616,91 @@ def pin_fill_invariants(lib_path=None, seed=37):
     assert np.array_equal(_fill(sh, f, [[z, x + 1, y]], lib_path)["tri"], base), "translation"
 
 
+# ------------------------------------------------------------ fill work counters
+# The fill roofline's algorithmic work: candidate polygons (boxes holding a
+# pixel centre), needed edges (crossed in y by a ray on one of their polygon's
+# centre rows, half-open as in the fill), (edge, row) crossings and
+# (pixel, candidate polygon) pairs.
+def _fillcnt(edges, first, tiles, lib_path=None):
+    return oracle.OraclePolygons(edges, first, merc01=True, lib_path=lib_path).counters(np.array(tiles))
+
+
+def pin_fillcnt_closed_forms(lib_path=None):
+    z, x, y = 9, 300, 200
+    t = [[z, x, y]]
+    # square [10.25, 20.75] x [30.25, 40.75]: centres 10.5..20.5 (11 columns)
+    # and 30.5..40.5 (11 rows); its two vertical sides cross all 11 rows, the
+    # horizontal ones none
+    e, f = _polys(z, x, y, [[_box(10.25, 30.25, 20.75, 40.75)]])
+    assert _fillcnt(e, f, t, lib_path).tolist() == [[1, 2, 22, 121]]
+    # a hole as a second ring: two more vertical sides over rows 33.5..36.5
+    e, f = _polys(z, x, y, [[_box(10.25, 30.25, 20.75, 40.75), _box(13.25, 33.25, 16.75, 36.75)]])
+    assert _fillcnt(e, f, t, lib_path).tolist() == [[1, 4, 30, 121]]
+    # two polygons: the counts add
+    e, f = _polys(z, x, y, [[_box(10.25, 30.25, 20.75, 40.75)], [_box(100.0, 100.0, 110.0, 105.0)]])
+    assert _fillcnt(e, f, t, lib_path).tolist() == [[2, 4, 22 + 10, 121 + 50]]
+    # a box between two centre columns holds no centre: no candidate
+    e, f = _polys(z, x, y, [[_box(10.6, 30.25, 11.4, 40.75)]])
+    assert _fillcnt(e, f, t, lib_path).tolist() == [[0, 0, 0, 0]]
+    # vertices on centre rows, half-open rule: an edge crosses the rows
+    # j + 0.5 in [min y, max y).  Diamond (50.5, 60) (70.5, 80.5) (50.5, 101)
+    # (30.5, 80.5): box rows and columns 60.5..100.5 and 30.5..70.5 (41 each);
+    # the upper sides cross 60.5..79.5 (20 rows each), the lower ones
+    # 80.5..100.5 (21 each)
+    e, f = _polys(z, x, y, [[[(50.5, 60.0), (70.5, 80.5), (50.5, 101.0), (30.5, 80.5)]]])
+    got = _fillcnt(e, f, t, lib_path).tolist()[0]
+    assert got == [1, 4, 20 + 20 + 21 + 21, 41 * 41], got
+    # a top vertex on a centre row, both sides going south to y = 80.2 and a
+    # horizontal base: each side crosses 60.5..79.5 (20 rows), the base none;
+    # box columns 30.5..69.5 (40) by rows 60.5..79.5 (20)
+    e, f = _polys(z, x, y, [[[(50.5, 60.5), (70.2, 80.2), (30.2, 80.2)]]])
+    got = _fillcnt(e, f, t, lib_path).tolist()[0]
+    assert got == [1, 2, 40, 800], got
+    # the tile next door along x sees nothing of the square
+    e, f = _polys(z, x, y, [[_box(10.25, 30.25, 20.75, 40.75)]])
+    assert _fillcnt(e, f, [[z, x + 1, y]], lib_path).tolist() == [[0, 0, 0, 0]]
+
+
+def _brute_fillcnt(edges, first, z, x, y):
+    """The four fill counters by enumeration over all 256 x 256 centres."""
+    S = 256.0 * 2.0 ** z
+    e = np.asarray(edges, dtype=np.float64).reshape(-1, 4)
+    ax, ay = e[:, 0] * S - 256.0 * x, e[:, 1] * S - 256.0 * y
+    bx, by = e[:, 2] * S - 256.0 * x, e[:, 3] * S - 256.0 * y
+    c = np.arange(256, dtype=np.float64) + 0.5
+    cand = need = pairs = px = 0
+    for p in range(len(first) - 1):
+        q = slice(first[p], first[p + 1])
+        x0, x1 = min(ax[q].min(), bx[q].min()), max(ax[q].max(), bx[q].max())
+        y0, y1 = min(ay[q].min(), by[q].min()), max(ay[q].max(), by[q].max())
+        cols = (c >= x0) & (c <= x1)
+        rows = (c >= y0) & (c <= y1)
+        if not cols.any() or not rows.any():
+            continue
+        cand += 1
+        px += int(cols.sum()) * int(rows.sum())
+        for k in range(first[p], first[p + 1]):
+            crossed = rows & ((ay[k] > c) != (by[k] > c))
+            if crossed.any():
+                need += 1
+                pairs += int(crossed.sum())
+    return cand, need, pairs, px
+
+
+def pin_fillcnt_brute(lib_path=None, seed=43):
+    rng = np.random.default_rng(seed)
+    for z in (5, 12):
+        x = int(rng.integers(1, (1 << z) - 1))
+        y = int(rng.integers(1, (1 << z) - 1))
+        e, f = _star_polys(rng, z, x, y, 30, spread=120.0)
+        tiles = [(z, x, y), (z, x + 1, y), (z, x, y - 1)]
+        got = _fillcnt(e, f, tiles, lib_path)
+        for k, tile in enumerate(tiles):
+            want = _brute_fillcnt(e, f, *tile)
+            assert tuple(int(v) for v in got[k]) == want, (tile, got[k].tolist(), want)
+        assert got[:, 0].sum() > 0 and got[:, 2].sum() > got[:, 1].sum()
+
+
 PINS = {
     "projection": pin_projection,
     "addressing": pin_addressing,
@@ -632,4 +717,6 @@ PINS = {
     "fill_invariants": pin_fill_invariants,
     "cnt_closed_forms": pin_cnt_closed_forms,
     "cnt_brute": pin_cnt_brute,
+    "fillcnt_closed_forms": pin_fillcnt_closed_forms,
+    "fillcnt_brute": pin_fillcnt_brute,
 }

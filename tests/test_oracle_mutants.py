@@ -55,6 +55,14 @@ MUTANTS = [
     ("cnt-box-half-height", "obox qr = { (cx - r) / S, (cy - r) / S, (cx + r) / S, (cy + r) / S };",
      "obox qr = { (cx - r) / S, (cy - r) / S, (cx + r) / S, cy / S };"),
     ("cnt-unlit-ambiguous-only", "if (!b && npix > 0) {", "if (t == 0 && npix > 0) {"),
+    # fill work counters (the fill roofline's algorithmic bytes and flops)
+    ("fillcnt-other-half-open", "const double rj0 = fmax(ceil(lo - 0.5), fj0), rj1 = fmin(ceil(hi - 0.5) - 1.0, fj1);",
+     "const double rj0 = fmax(floor(lo - 0.5) + 1.0, fj0), rj1 = fmin(floor(hi - 0.5), fj1);"),
+    ("fillcnt-no-tile-clip", "fj1 = fmin(floor(by1 - 0.5), 255.0);", "fj1 = floor(by1 - 0.5);"),
+    ("fillcnt-px-rows-only", "px += (int64_t)(fi1 - fi0 + 1.0) * (int64_t)(fj1 - fj0 + 1.0);",
+     "px += (int64_t)(fj1 - fj0 + 1.0);"),
+    ("fillcnt-need-per-row", "++need;\n                pairs +=", "need += (int64_t)(rj1 - rj0 + 1.0);\n                pairs +="),
+    ("fillcnt-box-corner", "const double fi0 = fmax(ceil(bx0 - 0.5), 0.0)", "const double fi0 = fmax(ceil(bx0), 0.0)"),
 ]
 
 
@@ -67,6 +75,6 @@ def test_mutant_is_caught(name, old, new, tmp_path):
     sys.path.insert(0, ROOT)
     from oracle import build as ob
     lib = ob.build(str(mut), str(tmp_path / "libmut.so"))
-    family = name.split("-")[0] + "_" if name.startswith(("aa-", "fill-", "cnt-")) else ""
+    family = name.split("-")[0] + "_" if name.startswith(("aa-", "fill-", "cnt-", "fillcnt-")) else ""
     res = subprocess.run([sys.executable, RUNNER, lib, family], capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"planted mistake {name!r} was not caught:\n{res.stdout}{res.stderr}"
