@@ -16,8 +16,9 @@ brute force of N_box and N_unlit_cand).  Per-zoom sums are kept beside the
 totals.
 
 Calls only the oracle and the seeded generators.  Usage:
-    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4] [c3]
-(c3: sampled and extrapolated per zoom, see c3_sampled).
+    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4] [c3] [c4fill]
+(c3: sampled and extrapolated per zoom, see c3_sampled; c4fill: the fill
+counters, see c4fill).
 """
 from __future__ import annotations
 
@@ -119,11 +120,56 @@ def c3_sampled(data):
     print(name, {k: v for k, v in data[name + "/zooms-3-18-extrapolated"].items() if k != "per_zoom"}, flush=True)
 
 
+def c4fill(data):
+    """Polygon filling of the 2e8-edge polygons over the same 4,096 requests
+    (Algorithm 2).  Per tile, from the oracle's fill counters:
+      bytes = 8192 (the mask) + 32 * needed edges (edges of a candidate
+              polygon -- its box holds a pixel centre -- that a ray on one of
+              its centre rows crosses in y: the crossings that decide some
+              pixel's parity);
+      flops = 5 per (edge, row) crossing (the crossing's x: two differences,
+              a product, a quotient, a sum) + 1 per (pixel, candidate polygon)
+              pair (its parity test)."""
+    name = "polygon-fill-2e8edges-4096mixed-z2-20"
+    t0 = time.time()
+    edges = hvgen.gen_c4_edges()
+    first = hvgen.c4_polygon_first(edges)
+    tiles, _ = hvgen.c4_requests(edges, n=4096)
+    n_edges, n_poly = int(edges.shape[0]), int(len(first) - 1)
+    print(f"{name}: {n_edges} edges, {n_poly} polygons, generated in {time.time() - t0:.1f}s", flush=True)
+    P = oracle.OraclePolygons(edges, first)
+    del edges
+    print(f"{name}: oracle polygons built, {time.time() - t0:.1f}s", flush=True)
+    cnt = P.counters(tiles)
+    del P
+    zooms = {}
+    for z in np.unique(tiles[:, 0]):
+        sel = tiles[:, 0] == z
+        cz = cnt[sel].sum(0)
+        zooms[str(int(z))] = {"tiles": int(sel.sum()), "alg_bytes": int(8192 * sel.sum() + 32 * cz[1]),
+                              "alg_flops": int(5 * cz[2] + cz[3]), "candidate_polygons": int(cz[0])}
+    c = cnt.sum(0)
+    n = len(tiles)
+    rec = {"tiles": n, "objects": n_edges, "polygons": n_poly, "candidate_polygons": int(c[0]),
+           "needed_edges": int(c[1]), "edge_row_crossings": int(c[2]), "pixel_polygon_pairs": int(c[3]),
+           "alg_bytes": int(8192 * n + 32 * c[1]), "alg_flops": int(5 * c[2] + c[3]),
+           "bytes_per_tile": (8192 * n + 32 * float(c[1])) / n, "per_zoom": zooms,
+           "note": "bytes = 8192 per mask + 32 per edge whose crossing decides some pixel's parity; flops = 5 per "
+                   "(edge, row) crossing + 1 per (pixel, candidate polygon) parity test"}
+    data[name] = rec
+    print(name, {k: v for k, v in rec.items() if k != "per_zoom"}, f"{time.time() - t0:.1f}s", flush=True)
+
+
 def main(keys):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     if "c3" in keys:
         keys = [k for k in keys if k != "c3"]
         c3_sampled(data)
+        with open(OUT, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+    if "c4fill" in keys:
+        keys = [k for k in keys if k != "c4fill"]
+        c4fill(data)
         with open(OUT, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
     for key in keys:
