@@ -114,6 +114,12 @@ def query_kernel_name(launch) -> str:
     return f"k_query<{L.get('block', 16) or 16}>"
 
 
+def fill_kernel_name(launch) -> str:
+    """Name of the fill kernel a launch shape runs (filling is region mode
+    only; region 32 by default)."""
+    return f"k_fill_region<{(launch or {}).get('region', 32) or 32}>"
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
@@ -173,18 +179,19 @@ def algorithmic_work(workload: str, zooms=None):
                             f"bound, so achieved and frac are lower bounds)"}
 
 
-def roofline_record(workload: str, launch, frontier_ms: float, query_ms: float, zooms=None):
+def roofline_record(workload: str, launch, frontier_ms: float, query_ms: float, zooms=None, kernel=None):
     """The query kernel against its roofline.  Algorithmic work per launch
     comes from the oracle's counters (algorithmic_work): bytes = masks + the
     objects unlit pixels need, flops = the exact distance tests those pixels
     need plus one witness per lit pixel.  The roofline time is max(bytes /
     8 TB/s, flops / 78.6 TFLOP/s); the larger term names the bound ("hbm" or
     "alu": FP64 vector arithmetic), and the other side is reported beside
-    it."""
+    it.  `kernel` names the measured kernel (default: the query kernel of
+    the launch shape)."""
     work = algorithmic_work(workload, zooms)
     if not work:
         return None
-    kname = query_kernel_name(launch)
+    kname = kernel or query_kernel_name(launch)
     sec = query_ms * 1e-3
     gbs = work["alg_bytes"] / sec / 1e9
     tfl = work["alg_flops"] / sec / 1e12
@@ -402,6 +409,10 @@ def fill_bench(args, hv, torch):
     step_ms = [a.elapsed_time(b) for a, b in evs]
     value = n * args.steps / wall
     stage(f"timed {args.steps} steps: {wall / args.steps * 1e3:.3f} ms/step")
+    # the fill kernel alone, HIP events on the stream it runs on
+    frontier_ms, fill_ms = hv.hv_time_fill(h, t4, out, launch, reps=max(args.steps, 3))
+    roofline = roofline_record(WORKLOADS["c4fill"]["name"], launch, frontier_ms, fill_ms,
+                               kernel=fill_kernel_name(launch))
     per_tile = None
     if not args.no_per_tile:
         pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
@@ -452,7 +463,7 @@ def fill_bench(args, hv, torch):
         "config": {"workload": WORKLOADS["c4fill"]["name"], "n_edges": int(edges.shape[0]),
                    "n_polygons": int(len(first) - 1), "zooms": "2-20", "requests_per_launch": n, "launch": launch},
         "fill": {"tiles_per_s": value, "step_p50_ms": pct(step_ms, 50), "step_p99_ms": pct(step_ms, 99)},
-        "per_tile_launch": per_tile, "build_ms": info["build_ms"], "roofline": None, "cpu_baseline": cpu,
+        "per_tile_launch": per_tile, "build_ms": info["build_ms"], "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
 

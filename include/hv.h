@@ -351,6 +351,15 @@ int hv_render_batch_noalloc(const hv_request *reqs, int64_t n, uint8_t *out_mask
 int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
                     double *ms);
 
+/* Kernel timing of polygon filling, for its roofline: hv_render_fill's
+ * arguments, rendered reps times, with HIP events on the calling thread's
+ * stream around the tile-frontier kernel and the fill kernel.  ms (host, 2
+ * entries) receives their mean durations in milliseconds (frontier, fill).
+ * Synchronous.  Errors as hv_render_fill, and HV_EINVAL for n_tiles < 1, reps
+ * outside [1, 100000] or ms NULL, before any device call. */
+int hv_time_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
+                 const hv_launch *launch, int32_t reps, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

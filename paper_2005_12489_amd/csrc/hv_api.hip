@@ -445,27 +445,29 @@ hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *
     return ix;
 }
 
-int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
-                   const hv_launch *launch) {
+// Checks a fill call and resolves its shape; *empty is set for n_tiles = 0
+// (nothing to launch).
+int prepare_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
+                 const hv_launch *launch, hv::LaunchShape *shape, bool *empty) {
+    *empty = false;
     if (!index) return fail(HV_EINVAL, "index is NULL");
     if (index->kind != HV_POLYGONS) return fail(HV_EINVAL, "hv_render_fill needs a polygon index");
     if (n_tiles < 0) return fail(HV_EINVAL, "n_tiles < 0");
     if (n_tiles > 0 && (!tiles || !out_masks)) return fail(HV_EINVAL, "tiles or out_masks is NULL");
     int rc = validate_tiles(tiles, n_tiles);
     if (rc) return rc;
-    hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, index->a.levels, &shape, n_tiles))) return rc;
+    if ((rc = resolve_shape(launch, index->a.levels, shape, n_tiles))) return rc;
     if (!launch) {
         // filling's default at every batch size: two waves per 32 x 32 region
-        shape.waves = 2;
-        shape.cand_cap = 256;
+        shape->waves = 2;
+        shape->cand_cap = 256;
     }
-    if (shape.region == 0) return fail(HV_EINVAL, "filling runs in region mode: launch.region must be 32 or 64");
-    shape.fill = 1;
-    if (hv::query_lds_bytes(shape, index->a.levels) > 65536)
+    if (shape->region == 0) return fail(HV_EINVAL, "filling runs in region mode: launch.region must be 32 or 64");
+    shape->fill = 1;
+    if (hv::query_lds_bytes(*shape, index->a.levels) > 65536)
         return fail(HV_EINVAL, "launch shape needs more than 64 KiB of LDS per workgroup");
     if (n_tiles == 0) {
-        t_err.clear();
+        *empty = true;
         return HV_OK;
     }
     if ((rc = validate_out(out_masks))) return rc;
@@ -474,11 +476,64 @@ int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles,
         if (hipGetDevice(&dev) != hipSuccess) return hip_status(hipGetLastError(), "hipGetDevice");
         if (dev != index->device) return fail(HV_EINVAL, "the index lives on another device");
     }
+    return HV_OK;
+}
+
+std::vector<hv::DevReq> fill_requests(const hv_tile *tiles, int64_t n_tiles) {
     std::vector<hv::DevReq> reqs((size_t)n_tiles);
     for (int64_t k = 0; k < n_tiles; ++k) reqs[(size_t)k] = hv::DevReq{tiles[k].z, tiles[k].x, tiles[k].y, 0, 0.0};
+    return reqs;
+}
+
+int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
+                   const hv_launch *launch) {
+    hv::LaunchShape shape;
+    bool empty = false;
+    int rc = prepare_fill(index, tiles, n_tiles, out_masks, launch, &shape, &empty);
+    if (rc) return rc;
+    if (empty) {
+        t_err.clear();
+        return HV_OK;
+    }
+    const std::vector<hv::DevReq> reqs = fill_requests(tiles, n_tiles);
     const hv::DevIndex dv = dev_view(index);
     rc = run_batch(&dv, 1, index->a.levels, reqs.data(), n_tiles, out_masks, shape, "hv_render_fill");
     if (rc) return rc;
+    t_err.clear();
+    return HV_OK;
+}
+
+int hv_time_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
+                 const hv_launch *launch, int32_t reps, double *ms) {
+    if (!ms) return fail(HV_EINVAL, "ms is NULL");
+    if (reps < 1 || reps > 100000) return fail(HV_EINVAL, "reps must be in [1, 100000]");
+    if (n_tiles <= 0) return fail(HV_EINVAL, "the batch is empty");
+    hv::LaunchShape shape;
+    bool empty = false;
+    int rc = prepare_fill(index, tiles, n_tiles, out_masks, launch, &shape, &empty);
+    if (rc) return rc;
+    const std::vector<hv::DevReq> reqs = fill_requests(tiles, n_tiles);
+    const hv::DevIndex dv = dev_view(index);
+    hipEvent_t m[3] = {nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&m[k]);
+    double sum[2] = {0.0, 0.0};
+    for (int rep = 0; rep < reps && e == hipSuccess && rc == HV_OK; ++rep) {
+        rc = run_batch(&dv, 1, index->a.levels, reqs.data(), n_tiles, out_masks, shape, "hv_time_fill", m);
+        if (rc) break;
+        if ((e = hipEventSynchronize(m[2])) != hipSuccess) break;
+        float a = 0, b = 0;
+        if ((e = hipEventElapsedTime(&a, m[0], m[1])) != hipSuccess) break;
+        if ((e = hipEventElapsedTime(&b, m[1], m[2])) != hipSuccess) break;
+        sum[0] += a;
+        sum[1] += b;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (m[k]) (void)hipEventDestroy(m[k]);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_status(e, "hv_time_fill");
+    ms[0] = sum[0] / reps;
+    ms[1] = sum[1] / reps;
     t_err.clear();
     return HV_OK;
 }
