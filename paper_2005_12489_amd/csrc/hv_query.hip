@@ -1185,6 +1185,7 @@ struct FillLds {
     int64_t *cpre;    // kFillGroup + 1 prefix sums of the group's chunk counts
     int64_t *lc;      // one per thread: chunks that passed their box test this round
     uint8_t *lq;      // and the group polygon each belongs to
+    uint8_t *ldir;    // kFillGroup: bit w set when the group polygon's rays in mask word column w run towards +x
     int *ctl;         // [0] stack size, [1] candidates, [2], [3] passed chunks (alternate rounds)
 };
 
@@ -1192,7 +1193,7 @@ __host__ __device__ inline size_t fill_lds_bytes(int cap, int levels, int thread
     const size_t rows = (size_t)rs * (rs / 32) * 4;
     return align16((size_t)region_stack_words(levels, threads) * 4) + 2 * align16((size_t)cap * 4) + align16(rows) +
            align16(kFillGroup * rows) + 2 * align16(kFillGroup * 8) + align16((kFillGroup + 1) * 8) +
-           align16((size_t)threads * 8) + align16((size_t)threads) + 16;
+           align16((size_t)threads * 8) + align16((size_t)threads) + align16(kFillGroup) + 16;
 }
 
 template <int RS>
@@ -1250,6 +1251,7 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
             if (tid < 64) {  // edge ranges of the group and the prefix sums of their chunk counts
                 int64_t f = 0, fe = 0;
                 long long x = 0;
+                uint8_t dir = 0;
                 // a polygon whose pixel centres in the region are all filled
                 // already cannot change the fill: it gets no chunks
                 const uint32_t rg = lane < nb ? L.crng[c0 + lane] : 0u;
@@ -1258,6 +1260,19 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                     f = ix.pfirst[pid];
                     fe = ix.pfirst[pid + 1];
                     x = fe > f ? (fe - 1) / kEdgeChunk - f / kEdgeChunk + 1 : 0;
+                    // Algorithm 2 casts each pixel's ray to the nearer x side of
+                    // the polygon's box.  Here the centre of each 32-pixel word
+                    // column picks the side for its pixels (the parity of a
+                    // closed ring is the same either way; a fixed column width
+                    // keeps centres on an edge alike in every launch shape), so
+                    // pixels in the right half of a polygon need only the edges
+                    // right of them
+                    const double4 bb = reinterpret_cast<const double4 *>(ix.obj)[pid];
+#pragma unroll
+                    for (int wd = 0; wd < W; ++wd) {
+                        const double wcx = i0 + 32.0 * wd + 16.0;
+                        if (wcx - (bb.x * S - ox) >= (bb.z * S - ox) - wcx) dir |= (uint8_t)(1u << wd);
+                    }
                 }
 #pragma unroll
                 for (int o = 1; o < kFillGroup; o <<= 1) {
@@ -1268,6 +1283,7 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                     L.efirst[lane] = f;
                     L.eend[lane] = fe;
                     L.cpre[lane + 1] = x;
+                    L.ldir[lane] = dir;
                 }
                 if (lane == 0) L.cpre[0] = 0;
             }
@@ -1292,9 +1308,15 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                     // power of two and rounding is monotonic), so a chunk with
                     // an edge the edge test below would use always passes
                     const float4 cb = ix.pchunk[c];
-                    pass = (double)cb.x * S - ox < i0 + (RS - 0.5) &&
-                           fmax(ceil((double)cb.y * S - oy - j0 - 0.5) - 1.0, 0.0) <=
-                               fmin(ceil((double)cb.w * S - oy - j0 - 0.5), RS - 1.0);
+                    // on the ray side of some centre: left of a word column's last
+                    // centre (rays to -x) or right of its first (rays to +x)
+                    const double cx0 = (double)cb.x * S - ox, cx1 = (double)cb.z * S - ox;
+                    bool side = false;
+#pragma unroll
+                    for (int wd = 0; wd < W; ++wd)
+                        side |= (L.ldir[q] >> wd) & 1u ? cx1 > i0 + 32.0 * wd + 0.5 : cx0 < i0 + 32.0 * wd + 31.5;
+                    pass = side && fmax(ceil((double)cb.y * S - oy - j0 - 0.5) - 1.0, 0.0) <=
+                                       fmin(ceil((double)cb.w * S - oy - j0 - 0.5), RS - 1.0);
                 }
                 const int slot = wave_alloc(npass, __ballot(pass), lane);
                 if (pass) {
@@ -1310,7 +1332,15 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                     if (e < L.efirst[qq] || e >= L.eend[qq]) continue;
                     const double4 gd = reinterpret_cast<const double4 *>(ix.pedges)[e];
                     const double ax = gd.x * S - ox, ay = gd.y * S - oy, bx = gd.z * S - ox, by = gd.w * S - oy;
-                    if (ay == by || fmin(ax, bx) >= i0 + (RS - 0.5)) continue;  // no crossing left of a pixel
+                    const uint32_t dir = L.ldir[qq];
+                    if (ay == by) continue;
+                    // no crossing on the ray side of any centre
+                    bool side = false;
+#pragma unroll
+                    for (int wd = 0; wd < W; ++wd)
+                        side |= (dir >> wd) & 1u ? fmax(ax, bx) > i0 + 32.0 * wd + 0.5
+                                                 : fmin(ax, bx) < i0 + 32.0 * wd + 31.5;
+                    if (!side) continue;
                     uint32_t *pq = par + qq * (RS * W);
                     // candidate rows, one wider on each side; each is checked exactly
                     const int jlo = (int)fmax(ceil(fmin(ay, by) - j0 - 0.5) - 1.0, 0.0);
@@ -1319,12 +1349,23 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                         const double yc = j0 + (double)j + 0.5;
                         if ((ay > yc) == (by > yc)) continue;
                         const double xc = ax + (yc - ay) * (bx - ax) / (by - ay);
-                        const double fx = floor(xc - i0 - 0.5) + 1.0;  // first pixel strictly right of xc
-                        if (fx >= RS) continue;
-                        const int k0 = fx <= 0.0 ? 0 : (int)fx;
-                        for (int wd = k0 >> 5; wd < W; ++wd) {
-                            const int lo = k0 - 32 * wd;
-                            atomicXor(&pq[j * W + wd], lo <= 0 ? 0xffffffffu : (0xffffffffu << lo));
+                        // the first pixel strictly right of xc and the last
+                        // strictly left of it, clamped to [-1, RS]
+                        const int k0 = (int)fmin(fmax(floor(xc - i0 - 0.5) + 1.0, -1.0), (double)RS);
+                        const int k1 = (int)fmin(fmax(ceil(xc - i0 - 0.5) - 1.0, -1.0), (double)RS);
+#pragma unroll
+                        for (int wd = 0; wd < W; ++wd) {
+                            uint32_t bits;
+                            if ((dir >> wd) & 1u) {
+                                // rays to +x: the crossing counts for the centres left of it
+                                const int hi = k1 - 32 * wd;
+                                bits = hi < 0 ? 0u : hi >= 31 ? 0xffffffffu : ((2u << hi) - 1u);
+                            } else {
+                                // rays to -x: for the centres right of it
+                                const int lo = k0 - 32 * wd;
+                                bits = lo <= 0 ? 0xffffffffu : lo >= 32 ? 0u : (0xffffffffu << lo);
+                            }
+                            if (bits) atomicXor(&pq[j * W + wd], bits);
                         }
                     }
                 }
@@ -1439,7 +1480,8 @@ __global__ __launch_bounds__(256) void k_fill_region(DevBatch B, int cap, int ma
     L.cpre = L.eend + align16(kFillGroup * 8) / 8;
     L.lc = L.cpre + align16((kFillGroup + 1) * 8) / 8;
     L.lq = reinterpret_cast<uint8_t *>(L.lc + blockDim.x);
-    L.ctl = reinterpret_cast<int *>(L.lq + align16(blockDim.x));
+    L.ldir = L.lq + align16(blockDim.x);
+    L.ctl = reinterpret_cast<int *>(L.ldir + align16(kFillGroup));
     // the group parity rows start at zero and every group clears what it used
     for (int k = threadIdx.x; k < kFillGroup * RS * (RS / 32); k += blockDim.x) L.par[k] = 0;
     __syncthreads();

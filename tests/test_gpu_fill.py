@@ -147,6 +147,37 @@ def test_fill_large_polygons_across_tiles(hv, torch):
     hv.hv_free(h)
 
 
+def test_fill_many_edge_rings_both_ray_sides(hv, torch):
+    """Rings of 20,000 and 5,000 vertices (an outer ring and its hole) that
+    span many regions of a tile: regions in a polygon's left half cast rays to
+    -x, those in its right half to +x (the nearer box side, as Algorithm 2
+    does per pixel); both must give the oracle's parity, next to a small
+    polygon in the hole and a long thin one across the tile."""
+    rng = np.random.default_rng(79)
+    z, x, y = 10, 300, 400
+
+    def ring(cx, cy, rho, k, wiggle):
+        ang = np.linspace(0.0, 2 * math.pi, k, endpoint=False)
+        rad = rho * (1.0 + wiggle * rng.uniform(-1.0, 1.0, k))
+        return list(zip(cx + rad * np.cos(ang), cy + 0.8 * rad * np.sin(ang)))
+
+    outer = ring(128.3, 131.7, 110.0, 20_000, 0.02)
+    hole = ring(120.1, 125.4, 45.0, 5_000, 0.05)
+    small = ring(118.6, 127.2, 9.0, 12, 0.1)
+    thin = [(2.2, 60.3), (250.7, 64.9), (250.7, 66.1), (2.2, 61.8)]
+    e, f = _group([[outer, hole], [small], [thin]], z, x, y)
+    h = build_polys(hv, torch, e, f, merc01=True)
+    tiles = [(z, x, y), (z, x + 1, y), (z, x, y + 1), (z + 1, 2 * x, 2 * y), (z + 1, 2 * x + 1, 2 * y + 1),
+             (z - 1, x // 2, y // 2)]
+    log("fill many-edge rings")
+    ref = oracle.OraclePolygons(e, f, merc01=True).render(tiles)["tri"]
+    for L in (None, dict(region=64, waves_per_wg=4, cand_cap=256), dict(region=32, waves_per_wg=1, cand_cap=64)):
+        got = fill(hv, torch, h, tiles, L)
+        check(got, ref, f"fill many-edge rings {L}")
+    assert got[0].sum() > 20000 and got[0, 128, 124] == 1 and got[0, 128, 110] == 0, "ring, hole, small polygon"
+    hv.hv_free(h)
+
+
 def test_fill_star_polygons_mixed_zooms(hv, torch):
     edges = hvgen.gen_c4_edges(min_edges=300_000, batch_polygons=4000)
     first = hvgen.c4_polygon_first(edges)
