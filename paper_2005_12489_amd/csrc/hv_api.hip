@@ -55,6 +55,7 @@ hv::DevIndex dev_view(const hv_index *ix) {
     d.pedges = ix->p.edges;
     d.pfirst = ix->p.first;
     d.pchunk = ix->p.chunks;
+    d.psuper = ix->p.supers;
     d.npoly = ix->p.npoly;
     return d;
 }

@@ -159,6 +159,21 @@ __global__ __launch_bounds__(256) void k_edge_chunks(const double *__restrict__ 
     chunks[c] = make_float4(float_down(x0), float_down(y0), float_up(x1), float_up(y1));
 }
 
+// Union of each run of kChunkSuper chunk boxes (already outward-rounded):
+// the upper level of the two-level box hierarchy over a polygon's edges.
+__global__ __launch_bounds__(256) void k_super_chunks(const float4 *__restrict__ chunks, int64_t nchunk,
+                                                      float4 *__restrict__ supers) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= (nchunk + kChunkSuper - 1) / kChunkSuper) return;
+    float4 b = chunks[s * kChunkSuper];
+    const int64_t c1 = min(nchunk, (s + 1) * kChunkSuper);
+    for (int64_t c = s * kChunkSuper + 1; c < c1; ++c) {
+        const float4 q = chunks[c];
+        b = make_float4(fminf(b.x, q.x), fminf(b.y, q.y), fmaxf(b.z, q.z), fmaxf(b.w, q.w));
+    }
+    supers[s] = b;
+}
+
 // Copies each polygon's edges from input order to the tree's order: wave w
 // of the grid moves sorted polygon w, whose edges start at src_first[order[w]]
 // in `src` and at dst_first[w] in `dst`.
@@ -421,6 +436,8 @@ void free_poly_arrays(PolyArrays *p) {
     if (p->edges) (void)hipFree(p->edges);
     if (p->first) (void)hipFree(p->first);
     if (p->chunks) (void)hipFree(p->chunks);
+    if (p->supers) (void)hipFree(p->supers);
+    p->supers = nullptr;
     p->edges = nullptr;
     p->first = nullptr;
     p->chunks = nullptr;
@@ -497,7 +514,10 @@ BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first,
     const int64_t nchunk = cdiv(n, kEdgeChunk);
     if ((e = hipMalloc((void **)&poly->edges, sizeof(double) * 4 * (size_t)n)) != hipSuccess) return bail(e);
     if ((e = hipMalloc((void **)&poly->first, sizeof(int64_t) * (size_t)(npoly + 1))) != hipSuccess) return bail(e);
+    const int64_t nsuper = cdiv(nchunk, kChunkSuper);
     if (nchunk > 0 && (e = hipMalloc((void **)&poly->chunks, sizeof(float4) * (size_t)nchunk)) != hipSuccess)
+        return bail(e);
+    if (nsuper > 0 && (e = hipMalloc((void **)&poly->supers, sizeof(float4) * (size_t)nsuper)) != hipSuccess)
         return bail(e);
     if ((e = hipMemcpyAsync(poly->first, sorted_first.data(), sizeof(int64_t) * (size_t)(npoly + 1),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -505,14 +525,17 @@ BuildResult build_polygons(const double *edges, int64_t n, const int64_t *first,
     hipLaunchKernelGGL(k_permute_polygons, dim3((uint32_t)cdiv(npoly, 4)), dim3(256), 0, st,
                        reinterpret_cast<const double4 *>(proj), in_first, tree->order, poly->first, npoly,
                        reinterpret_cast<double4 *>(poly->edges));
-    if (nchunk > 0)
+    if (nchunk > 0) {
         hipLaunchKernelGGL(k_edge_chunks, dim3((uint32_t)cdiv(nchunk, 256)), dim3(256), 0, st, poly->edges, n,
                            poly->chunks);
+        hipLaunchKernelGGL(k_super_chunks, dim3((uint32_t)cdiv(nsuper, 256)), dim3(256), 0, st, poly->chunks,
+                           nchunk, poly->supers);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return bail(e);
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e);
     release();
     tree->device_bytes += (int64_t)(sizeof(double) * 4 * (size_t)n + sizeof(int64_t) * (size_t)(npoly + 1) +
-                                    sizeof(float4) * (size_t)nchunk);
+                                    sizeof(float4) * (size_t)(nchunk + nsuper));
     return r;
 }
 

@@ -12,6 +12,7 @@ namespace hv {
 constexpr int kLeaf = 16;        // objects per leaf
 constexpr int kFan = 16;         // children per inner node
 constexpr int kEdgeChunk = 8;    // polygon edges per chunk box (filling)
+constexpr int kChunkSuper = 8;   // chunk boxes per super-chunk box (filling)
 constexpr int kFrontier = 256;   // most nodes in a tile's frontier
 constexpr int kMaxLevels = 16;   // node levels (2e9 objects need 8)
 constexpr int kLevelShift = 27;  // stack entry: level << 27 | node index
@@ -33,6 +34,7 @@ struct DevIndex {
     const double *pedges;        // edges, 4 doubles each, polygon after polygon in sorted order
     const int64_t *pfirst;       // the polygon at sorted position k owns edges [pfirst[k], pfirst[k + 1])
     const float4 *pchunk;        // chunk c: a box holding edges [kEdgeChunk c, kEdgeChunk (c + 1))
+    const float4 *psuper;        // super-chunk s: a box holding chunks [kChunkSuper s, kChunkSuper (s + 1))
     int64_t npoly;
 };
 
@@ -71,6 +73,7 @@ struct PolyArrays {
     double *edges = nullptr;     // projected, polygon after polygon in the tree's sorted order
     int64_t *first = nullptr;    // npoly + 1 offsets into edges, by sorted position
     float4 *chunks = nullptr;    // ceil(n_edges / kEdgeChunk) conservative float boxes
+    float4 *supers = nullptr;    // ceil(chunks / kChunkSuper) unions of chunk boxes
     int64_t npoly = 0, n_edges = 0;
 };
 

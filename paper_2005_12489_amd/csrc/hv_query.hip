@@ -1186,14 +1186,22 @@ struct FillLds {
     int64_t *lc;      // one per thread: chunks that passed their box test this round
     uint8_t *lq;      // and the group polygon each belongs to
     uint8_t *ldir;    // kFillGroup: bit w set when the group polygon's rays in mask word column w run towards +x
-    int *ctl;         // [0] stack size, [1] candidates, [2], [3] passed chunks (alternate rounds)
+    int64_t *spre;    // kFillGroup + 1 prefix sums of the group's super-chunk counts
+    int64_t *ls;      // one per thread: super-chunks that passed their box test this round
+    uint8_t *lsq;     // and the group polygon each belongs to
+    int *ctl;         // [0] stack size, [1] candidates, [2], [3] passed chunks (alternate rounds), [4] passed supers
 };
+
+// A group whose polygons hold at most this many chunk boxes per thread tests
+// them all; beyond, it tests the super-chunk boxes first.
+constexpr int kFlatChunkRounds = 4;
 
 __host__ __device__ inline size_t fill_lds_bytes(int cap, int levels, int threads, int rs) {
     const size_t rows = (size_t)rs * (rs / 32) * 4;
     return align16((size_t)region_stack_words(levels, threads) * 4) + 2 * align16((size_t)cap * 4) + align16(rows) +
            align16(kFillGroup * rows) + 2 * align16(kFillGroup * 8) + align16((kFillGroup + 1) * 8) +
-           align16((size_t)threads * 8) + align16((size_t)threads) + align16(kFillGroup) + 16;
+           align16((size_t)threads * 8) + align16((size_t)threads) + align16(kFillGroup) +
+           align16((kFillGroup + 1) * 8) + align16((size_t)threads * 8) + align16((size_t)threads) + 32;
 }
 
 template <int RS>
@@ -1228,6 +1236,7 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
         ctl[1] = 0;
         ctl[2] = 0;
         ctl[3] = 0;
+        ctl[4] = 0;
     }
     __syncthreads();
     for (int base = 0; base < fcount; base += nthr) {
@@ -1250,7 +1259,7 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
             const int nb = min(kFillGroup, nc - c0);
             if (tid < 64) {  // edge ranges of the group and the prefix sums of their chunk counts
                 int64_t f = 0, fe = 0;
-                long long x = 0;
+                long long x = 0, xs = 0;
                 uint8_t dir = 0;
                 // a polygon whose pixel centres in the region are all filled
                 // already cannot change the fill: it gets no chunks
@@ -1260,6 +1269,8 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                     f = ix.pfirst[pid];
                     fe = ix.pfirst[pid + 1];
                     x = fe > f ? (fe - 1) / kEdgeChunk - f / kEdgeChunk + 1 : 0;
+                    constexpr int kSuperEdges = kEdgeChunk * kChunkSuper;
+                    xs = fe > f ? (fe - 1) / kSuperEdges - f / kSuperEdges + 1 : 0;
                     // Algorithm 2 casts each pixel's ray to the nearer x side of
                     // the polygon's box.  Here the centre of each 32-pixel word
                     // column picks the side for its pixels (the parity of a
@@ -1277,54 +1288,42 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
 #pragma unroll
                 for (int o = 1; o < kFillGroup; o <<= 1) {
                     const long long y = __shfl_up(x, o, 64);
-                    if (lane >= o) x += y;
+                    const long long ys = __shfl_up(xs, o, 64);
+                    if (lane >= o) {
+                        x += y;
+                        xs += ys;
+                    }
                 }
                 if (lane < nb) {
                     L.efirst[lane] = f;
                     L.eend[lane] = fe;
                     L.cpre[lane + 1] = x;
+                    L.spre[lane + 1] = xs;
                     L.ldir[lane] = dir;
                 }
-                if (lane == 0) L.cpre[0] = 0;
+                if (lane == 0) {
+                    L.cpre[0] = 0;
+                    L.spre[0] = 0;
+                }
             }
             __syncthreads();
-            // rounds of nthr chunks: each lane tests one chunk box, then the
-            // edges of the chunks that passed are dealt out one per lane
-            const int64_t tot = L.cpre[nb];
-            int round = 0;
-            for (int64_t base = 0; base < tot; base += nthr, ++round) {
-                int *npass = &ctl[2 + (round & 1)];
-                const int64_t g = base + tid;
-                bool pass = false;
-                int q = 0;
-                int64_t c = 0;
-                if (g < tot) {
-                    // the group's polygon holding chunk g: largest q with cpre[q] <= g
+            // A chunk or super-chunk box of group polygon q can hold an edge the
+            // edge stage below would use: on the ray side of some centre (left
+            // of a word column's last centre for rays to -x, right of its first
+            // for rays to +x) and spanning a region row.  The boxes bound every
+            // edge's pixel coordinates (S is a power of two and rounding is
+            // monotonic), so such an edge's box always passes.
+            auto box_pass = [&](const float4 cb, int q) -> bool {
+                const double cx0 = (double)cb.x * S - ox, cx1 = (double)cb.z * S - ox;
+                bool side = false;
 #pragma unroll
-                    for (int h = kFillGroup / 2; h > 0; h >>= 1)
-                        if (q + h < nb && L.cpre[q + h] <= g) q += h;
-                    c = L.efirst[q] / kEdgeChunk + (g - L.cpre[q]);
-                    // the box bounds every edge's pixel coordinates (S is a
-                    // power of two and rounding is monotonic), so a chunk with
-                    // an edge the edge test below would use always passes
-                    const float4 cb = ix.pchunk[c];
-                    // on the ray side of some centre: left of a word column's last
-                    // centre (rays to -x) or right of its first (rays to +x)
-                    const double cx0 = (double)cb.x * S - ox, cx1 = (double)cb.z * S - ox;
-                    bool side = false;
-#pragma unroll
-                    for (int wd = 0; wd < W; ++wd)
-                        side |= (L.ldir[q] >> wd) & 1u ? cx1 > i0 + 32.0 * wd + 0.5 : cx0 < i0 + 32.0 * wd + 31.5;
-                    pass = side && fmax(ceil((double)cb.y * S - oy - j0 - 0.5) - 1.0, 0.0) <=
-                                       fmin(ceil((double)cb.w * S - oy - j0 - 0.5), RS - 1.0);
-                }
-                const int slot = wave_alloc(npass, __ballot(pass), lane);
-                if (pass) {
-                    L.lc[slot] = c;
-                    L.lq[slot] = (uint8_t)q;
-                }
-                __syncthreads();
-                const int np = *npass;
+                for (int wd = 0; wd < W; ++wd)
+                    side |= (L.ldir[q] >> wd) & 1u ? cx1 > i0 + 32.0 * wd + 0.5 : cx0 < i0 + 32.0 * wd + 31.5;
+                return side && fmax(ceil((double)cb.y * S - oy - j0 - 0.5) - 1.0, 0.0) <=
+                                   fmin(ceil((double)cb.w * S - oy - j0 - 0.5), RS - 1.0);
+            };
+            // the edges of the np chunks listed in L.lc / L.lq, one per lane
+            auto edges_of = [&](int np) {
                 for (int it = tid; it < np * kEdgeChunk; it += nthr) {
                     const int sl = it / kEdgeChunk;
                     const int qq = L.lq[sl];
@@ -1369,10 +1368,84 @@ __device__ __forceinline__ void fill_query(const DevIndex &ix, const DevReq &rq,
                         }
                     }
                 }
+            };
+            // One round: each lane tests the chunk its index gives (if any),
+            // the passing chunks are listed, and their edges dealt out.
+            int round = 0;
+            auto chunk_round = [&](bool have, int64_t c, int q) {
+                int *npass = &ctl[2 + (round & 1)];
+                const bool pass = have && box_pass(ix.pchunk[c], q);
+                const int slot = wave_alloc(npass, __ballot(pass), lane);
+                if (pass) {
+                    L.lc[slot] = c;
+                    L.lq[slot] = (uint8_t)q;
+                }
+                __syncthreads();
+                edges_of(*npass);
                 __syncthreads();
                 // this round's counter is free again (the next round uses the
                 // other one, cleared before this round's first barrier)
                 if (tid == 0) *npass = 0;
+                ++round;
+            };
+            const int64_t tot = L.cpre[nb];
+            if (tot <= (int64_t)kFlatChunkRounds * nthr) {
+                // few chunks: every chunk box is tested, nthr per round
+                for (int64_t base = 0; base < tot; base += nthr) {
+                    const int64_t g = base + tid;
+                    int q = 0;
+                    int64_t c = 0;
+                    if (g < tot) {
+                        // the group's polygon holding chunk g: largest q with cpre[q] <= g
+#pragma unroll
+                        for (int h = kFillGroup / 2; h > 0; h >>= 1)
+                            if (q + h < nb && L.cpre[q + h] <= g) q += h;
+                        c = L.efirst[q] / kEdgeChunk + (g - L.cpre[q]);
+                    }
+                    chunk_round(g < tot, c, q);
+                }
+            } else {
+                // many chunks (polygons with many edges): the super-chunk boxes
+                // first, nthr per round, then only the chunks of those that pass
+                const int64_t stot = L.spre[nb];
+                for (int64_t base = 0; base < stot; base += nthr) {
+                    const int64_t g = base + tid;
+                    bool pass = false;
+                    int q = 0;
+                    int64_t sc = 0;
+                    if (g < stot) {
+#pragma unroll
+                        for (int h = kFillGroup / 2; h > 0; h >>= 1)
+                            if (q + h < nb && L.spre[q + h] <= g) q += h;
+                        sc = L.efirst[q] / (kEdgeChunk * kChunkSuper) + (g - L.spre[q]);
+                        pass = box_pass(ix.psuper[sc], q);
+                    }
+                    const int slot = wave_alloc(&ctl[4], __ballot(pass), lane);
+                    if (pass) {
+                        L.ls[slot] = sc;
+                        L.lsq[slot] = (uint8_t)q;
+                    }
+                    __syncthreads();
+                    const int ns = ctl[4];
+                    for (int cb = 0; cb < ns * kChunkSuper; cb += nthr) {
+                        const int it = cb + tid;
+                        bool have = false;
+                        int q2 = 0;
+                        int64_t c = 0;
+                        if (it < ns * kChunkSuper) {
+                            const int sl = it / kChunkSuper;
+                            q2 = L.lsq[sl];
+                            c = L.ls[sl] * kChunkSuper + it % kChunkSuper;
+                            // only the polygon's own chunks of the super-chunk
+                            have = c >= L.efirst[q2] / kEdgeChunk && c <= (L.eend[q2] - 1) / kEdgeChunk;
+                        }
+                        chunk_round(have, c, q2);
+                    }
+                    // every lane has read ctl[4] and the list before it is reset
+                    __syncthreads();
+                    if (tid == 0) ctl[4] = 0;
+                    __syncthreads();
+                }
             }
             __syncthreads();
             bool full = true;
@@ -1481,7 +1554,10 @@ __global__ __launch_bounds__(256) void k_fill_region(DevBatch B, int cap, int ma
     L.lc = L.cpre + align16((kFillGroup + 1) * 8) / 8;
     L.lq = reinterpret_cast<uint8_t *>(L.lc + blockDim.x);
     L.ldir = L.lq + align16(blockDim.x);
-    L.ctl = reinterpret_cast<int *>(L.ldir + align16(kFillGroup));
+    L.spre = reinterpret_cast<int64_t *>(L.ldir + align16(kFillGroup));
+    L.ls = L.spre + align16((kFillGroup + 1) * 8) / 8;
+    L.lsq = reinterpret_cast<uint8_t *>(L.ls + blockDim.x);
+    L.ctl = reinterpret_cast<int *>(L.lsq + align16(blockDim.x));
     // the group parity rows start at zero and every group clears what it used
     for (int k = threadIdx.x; k < kFillGroup * RS * (RS / 32); k += blockDim.x) L.par[k] = 0;
     __syncthreads();
