@@ -268,7 +268,7 @@ def cpu_baseline(objs, kind, tiles, r, seconds: float, zmin: int = 0):
         order = rng.permutation(len(tiles))
         note = f"requests drawn at random (seed 12345) from the {len(tiles)}; index over all {objs.shape[0]} objects"
     else:
-        per = 3
+        per = 5
         order = np.concatenate([rng.permutation(np.nonzero(tiles[:, 0] == z)[0])[:per] for z in zs])
         order = order[rng.permutation(len(order))]
         stage(f"oracle baseline: selecting the objects near {len(order)} sampled requests")
