@@ -17,8 +17,11 @@ oracle's lit bits (tri-state 1) and ambiguous bits (tri-state 2), packed
 least significant bit first in the masks' layout, and a fingerprint of the
 generated inputs (helpers.input_fingerprint) that the test recomputes.
 
+  fullsize_c4_aa.npz  the 2e8 edges' anti-aliased values (oracle, exact mode)
+                   for 4 requests per zoom (76 tiles).
+
 Calls only the oracle and the seeded generators.  Usage:
-    python tests/golden/make_fullsize_parity.py [c4] [c3]
+    python tests/golden/make_fullsize_parity.py [c4] [c3] [c4aa]
 """
 from __future__ import annotations
 
@@ -38,6 +41,7 @@ import oracle  # noqa: E402
 from helpers import input_fingerprint, stratified_sample  # noqa: E402
 
 PER_ZOOM = 27
+PER_ZOOM_AA = 4
 ZMIN_C3 = 3
 SEED = 4040
 T0 = time.time()
@@ -75,6 +79,34 @@ def c4():
     tri = render_all(ix, tiles, r, idx)
     save(os.path.join(HERE, "fullsize_c4.npz"), idx, tiles, r, tri, fp,
          f"{PER_ZOOM} requests per zoom (seed {SEED}); oracle over all edges")
+
+
+def c4aa():
+    """Anti-aliased values (Algorithm 1's 0-4, the oracle's exact mode) of 4
+    requests per zoom of the 2e8 edges: per pixel the value, the number of
+    its sub-samples within 1e-6 px of r (ambiguous) and the number certainly
+    within r."""
+    edges = hvgen.gen_c4_edges()
+    tiles, r = hvgen.c4_requests(edges, n=4096)
+    fp = input_fingerprint(edges[::1000], edges.shape[0], tiles, r)
+    idx = stratified_sample(tiles, PER_ZOOM_AA, SEED + 1)
+    log(f"c4aa: {edges.shape[0]} edges, {len(idx)} sampled requests; building the oracle index")
+    ix = oracle.OracleIndex(edges, oracle.POLYGON_EDGES)
+    del edges
+    val = np.empty((len(idx), 256, 256), dtype=np.uint8)
+    amb = np.empty_like(val)
+    sure = np.empty_like(val)
+    for s in range(0, len(idx), 8):
+        sel = idx[s:s + 8]
+        o = ix.render_aa(tiles[sel], r[sel])
+        val[s:s + len(sel)], amb[s:s + len(sel)], sure[s:s + len(sel)] = o["val"], o["amb"], o["sure"]
+        log(f"c4aa: rendered {s + len(sel)}/{len(idx)}")
+    path = os.path.join(HERE, "fullsize_c4_aa.npz")
+    np.savez_compressed(path, idx=idx, tiles=tiles[idx], r=r[idx], val=val, amb=amb, sure=sure,
+                        fingerprint=np.array(fp),
+                        note=np.array(f"{PER_ZOOM_AA} requests per zoom (seed {SEED + 1}); oracle (exact mode) "
+                                      "over all edges"))
+    log(f"wrote {path}: {len(idx)} tiles, {int((val > 0).sum())} nonzero, {int(amb.sum())} ambiguous sub-samples")
 
 
 def _cell_of(pts):
@@ -128,4 +160,4 @@ def c3():
 
 if __name__ == "__main__":
     for key in sys.argv[1:] or ["c4", "c3"]:
-        {"c4": c4, "c3": c3}[key]()
+        {"c4": c4, "c3": c3, "c4aa": c4aa}[key]()
