@@ -19,9 +19,11 @@ generated inputs (helpers.input_fingerprint) that the test recomputes.
 
   fullsize_c4_aa.npz  the 2e8 edges' anti-aliased values (oracle, exact mode)
                    for 4 requests per zoom (76 tiles).
+  fullsize_c4_fill.npz  the fill masks of their 1,961,254 polygons for 27
+                   requests per zoom (513 tiles), the oracle over all polygons.
 
 Calls only the oracle and the seeded generators.  Usage:
-    python tests/golden/make_fullsize_parity.py [c4] [c3] [c4aa]
+    python tests/golden/make_fullsize_parity.py [c4] [c3] [c4aa] [c4fill]
 """
 from __future__ import annotations
 
@@ -109,6 +111,26 @@ def c4aa():
     log(f"wrote {path}: {len(idx)} tiles, {int((val > 0).sum())} nonzero, {int(amb.sum())} ambiguous sub-samples")
 
 
+def c4fill():
+    """Fill masks (Algorithm 2) of the 2e8 edges' polygons for 27 requests
+    per zoom, by an oracle over all 1,961,254 polygons."""
+    edges = hvgen.gen_c4_edges()
+    first = hvgen.c4_polygon_first(edges)
+    tiles, r = hvgen.c4_requests(edges, n=4096)
+    fp = input_fingerprint(edges[::1000], edges.shape[0], tiles, r)
+    idx = stratified_sample(tiles, PER_ZOOM, SEED + 2)
+    log(f"c4fill: {len(first) - 1} polygons, {len(idx)} sampled requests; building the oracle")
+    P = oracle.OraclePolygons(edges, first)
+    del edges
+    tri = np.empty((len(idx), 256, 256), dtype=np.uint8)
+    for s in range(0, len(idx), 8):
+        sel = idx[s:s + 8]
+        tri[s:s + len(sel)] = P.render(tiles[sel])["tri"]
+        log(f"c4fill: rendered {s + len(sel)}/{len(idx)}")
+    save(os.path.join(HERE, "fullsize_c4_fill.npz"), idx, tiles, r, tri, fp,
+         f"{PER_ZOOM} requests per zoom (seed {SEED + 2}); fill oracle over all polygons")
+
+
 def _cell_of(pts):
     """Zoom-8 cell (row-major, 256 x 256) of each point: chooses which points a
     tile's host index holds (own projection; the oracle projects them itself)."""
@@ -160,4 +182,4 @@ def c3():
 
 if __name__ == "__main__":
     for key in sys.argv[1:] or ["c4", "c3"]:
-        {"c4": c4, "c3": c3, "c4aa": c4aa}[key]()
+        {"c4": c4, "c3": c3, "c4aa": c4aa, "c4fill": c4fill}[key]()

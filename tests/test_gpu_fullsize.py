@@ -261,7 +261,7 @@ def test_c4_fill_full_size(hv, torch):
     log("c4 fill full size: generate 2e8 edges")
     edges = hvgen.gen_c4_edges()
     first = hvgen.c4_polygon_first(edges)
-    tiles, _ = hvgen.c4_requests(edges, n=4096)
+    tiles, r = hvgen.c4_requests(edges, n=4096)
     log(f"c4 fill full size: {len(first) - 1} polygons, 4096 requests")
     full = _fill(hv, torch, edges, first, tiles)
     # the fill of a set of polygons is the OR of the fills of any split of it
@@ -276,3 +276,5 @@ def test_c4_fill_full_size(hv, torch):
     pick = np.concatenate([_deep_sample(tiles, 6, zmin=8), low])
     log(f"c4 fill full size: oracle on {len(pick)} sampled tiles")
     _check_fill_sample(full, edges, first, tiles, pick, "c4-fill-full")
+    log("c4 fill full size: stored oracle masks of 27 requests per zoom at zooms 2-20")
+    _check_golden(full, "c4_fill", edges, tiles, r, "c4-fill-full")
