@@ -315,7 +315,7 @@ int64_t hv_estimate_bytes(const hv_index *index, const hv_tile *tile, const hv_s
 /* Device memory of a whole batch of n_requests requests over n_indexes
  * distinct indexes: its workspace (header, index table, requests and
  * per-request records, each array aligned to 256 bytes) plus the masks.  It
- * is at most n_requests * hv_estimate_bytes(...) + 2304 + 80 * n_indexes
+ * is at most n_requests * hv_estimate_bytes(...) + 2304 + 96 * n_indexes
  * bytes.  Returns the bytes, or HV_EINVAL for a negative count or more than
  * 4096 indexes. */
 int64_t hv_estimate_batch_bytes(int64_t n_requests, int32_t n_indexes);

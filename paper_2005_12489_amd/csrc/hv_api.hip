@@ -721,6 +721,7 @@ int64_t hv_estimate_bytes(const hv_index *index, const hv_tile *tile, const hv_s
 }
 
 int64_t hv_estimate_batch_bytes(int64_t n_requests, int32_t n_indexes) {
+    static_assert(sizeof(hv::DevIndex) == 96, "hv.h documents 96 bytes per index of a batch");
     if (n_requests < 0 || n_indexes < 0 || n_indexes > 4096)
         return fail(HV_EINVAL, "n_requests < 0 or n_indexes outside [0, 4096]");
     const hv::Workspace w = hv::workspace_layout(n_requests, n_indexes);

@@ -94,7 +94,7 @@ int main() {
     CHECK(hv_estimate_bytes(nullptr, &ok_tiles[0], &st) == HV_EINVAL);
     for (int64_t n : {0LL, 1LL, 255LL, 4096LL, 1LL << 24}) {
         const int64_t b = hv_estimate_batch_bytes(n, 5);
-        CHECK(b >= n * per && b <= n * per + 2304 + 80 * 5);
+        CHECK(b >= n * per && b <= n * per + 2304 + 96 * 5);
     }
     CHECK(hv_estimate_batch_bytes(-1, 1) == HV_EINVAL);
     CHECK(hv_estimate_batch_bytes(1, 5000) == HV_EINVAL);

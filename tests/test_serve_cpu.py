@@ -218,7 +218,7 @@ def test_request_bytes_follow_the_workspace_layout():
     rng = np.random.default_rng(3)
     for n, k in zip(rng.integers(0, 100_000, 50), rng.integers(1, 40, 50)):
         b = hv.hv_estimate_batch_bytes(int(n), int(k))
-        assert n * per <= b <= n * per + 2304 + 80 * k, (n, k, b)
+        assert n * per <= b <= n * per + 2304 + 96 * k, (n, k, b)
     h = hv.hv_index_build(None, hv.HV_POINTS, 0)
     try:
         for tile, r in (((23, 0, 0), 1.0), ((3, 8, 0), 1.0), ((3, 1, 1), 0.0), ((3, 1, 1), 65.0)):
