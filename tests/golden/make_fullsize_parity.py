@@ -21,9 +21,11 @@ generated inputs (helpers.input_fingerprint) that the test recomputes.
                    for 4 requests per zoom (76 tiles).
   fullsize_c4_fill.npz  the fill masks of their 1,961,254 polygons for 27
                    requests per zoom (513 tiles), the oracle over all polygons.
+  fullsize_c3_aa.npz  the 1e9 points' anti-aliased values (oracle, exact mode)
+                   for 4 requests per zoom at zooms >= ZMIN_C3 (64 tiles).
 
 Calls only the oracle and the seeded generators.  Usage:
-    python tests/golden/make_fullsize_parity.py [c4] [c3] [c4aa] [c4fill]
+    python tests/golden/make_fullsize_parity.py [c4] [c3] [c4aa] [c4fill] [c3aa]
 """
 from __future__ import annotations
 
@@ -140,10 +142,10 @@ def _cell_of(pts):
     return (np.clip(cy, 0, 255) * 256 + np.clip(cx, 0, 255)).astype(np.uint16)
 
 
-def c3():
+def _c3_points_by_cell():
+    """The 1e9 points sorted by zoom-8 cell, with the cells' start offsets."""
     n = 1_000_000_000
     tiles, r = hvgen.c3_requests(10_000)
-    idx = stratified_sample(tiles, PER_ZOOM, SEED, zmin=ZMIN_C3)
     pts = hvgen.gen_c3_points(n)
     fp = input_fingerprint(pts[::1000], n, tiles, r)
     log(f"c3: {n} points generated; sorting by zoom-8 cell")
@@ -156,19 +158,30 @@ def c3():
     del cells
     pts = pts[order]
     del order
+    return pts, start, tiles, r, fp
+
+
+def _c3_near(pts, start, tile):
+    """The points of the zoom-8 cells a tile covers and of the cells around them."""
+    z, x, y = (int(v) for v in tile)
+    if z >= 8:
+        x0 = x1 = x >> (z - 8)
+        y0 = y1 = y >> (z - 8)
+    else:
+        x0, x1 = x << (8 - z), ((x + 1) << (8 - z)) - 1
+        y0, y1 = y << (8 - z), ((y + 1) << (8 - z)) - 1
+    xa, xb = max(0, x0 - 1), min(255, x1 + 1)
+    return np.concatenate([pts[start[cy * 256 + xa]:start[cy * 256 + xb + 1]]
+                           for cy in range(max(0, y0 - 1), min(255, y1 + 1) + 1)])
+
+
+def c3():
+    pts, start, tiles, r, fp = _c3_points_by_cell()
+    idx = stratified_sample(tiles, PER_ZOOM, SEED, zmin=ZMIN_C3)
     tri = np.empty((len(idx), 256, 256), dtype=np.uint8)
     for k, t in enumerate(idx):
-        z, x, y = (int(v) for v in tiles[t])
-        if z >= 8:
-            x0 = x1 = x >> (z - 8)
-            y0 = y1 = y >> (z - 8)
-        else:
-            x0, x1 = x << (8 - z), ((x + 1) << (8 - z)) - 1
-            y0, y1 = y << (8 - z), ((y + 1) << (8 - z)) - 1
-        xa, xb = max(0, x0 - 1), min(255, x1 + 1)
-        parts = [pts[start[cy * 256 + xa]:start[cy * 256 + xb + 1]]
-                 for cy in range(max(0, y0 - 1), min(255, y1 + 1) + 1)]
-        sub = np.concatenate(parts)
+        z = int(tiles[t, 0])
+        sub = _c3_near(pts, start, tiles[t])
         if len(sub) == 0:
             tri[k] = 0
             continue
@@ -180,6 +193,29 @@ def c3():
          "over the points of the zoom-8 cells it covers and the cells around them")
 
 
+def c3aa():
+    """Anti-aliased values (oracle, exact mode) of 4 requests per zoom of the
+    1e9 points at zooms >= ZMIN_C3, each tile against an oracle index over the
+    points near it (the margin, a zoom-8 cell, exceeds r + 1/4 px)."""
+    pts, start, tiles, r, fp = _c3_points_by_cell()
+    idx = stratified_sample(tiles, PER_ZOOM_AA, SEED + 3, zmin=ZMIN_C3)
+    val = np.zeros((len(idx), 256, 256), dtype=np.uint8)
+    amb = np.zeros_like(val)
+    sure = np.zeros_like(val)
+    for k, t in enumerate(idx):
+        sub = _c3_near(pts, start, tiles[t])
+        if len(sub):
+            o = oracle.OracleIndex(sub, oracle.POINTS).render_aa(tiles[t:t + 1], r[t:t + 1])
+            val[k], amb[k], sure[k] = o["val"][0], o["amb"][0], o["sure"][0]
+        log(f"c3aa: tile {k + 1}/{len(idx)} z{int(tiles[t, 0])}: {len(sub)} points near")
+    path = os.path.join(HERE, "fullsize_c3_aa.npz")
+    np.savez_compressed(path, idx=idx, tiles=tiles[idx], r=r[idx], val=val, amb=amb, sure=sure,
+                        fingerprint=np.array(fp),
+                        note=np.array(f"{PER_ZOOM_AA} requests per zoom at zooms >= {ZMIN_C3} (seed {SEED + 3}); "
+                                      "oracle (exact mode) over the points near each tile"))
+    log(f"wrote {path}: {len(idx)} tiles, {int((val > 0).sum())} nonzero, {int(amb.sum())} ambiguous sub-samples")
+
+
 if __name__ == "__main__":
     for key in sys.argv[1:] or ["c4", "c3"]:
-        {"c4": c4, "c3": c3, "c4aa": c4aa, "c4fill": c4fill}[key]()
+        {"c4": c4, "c3": c3, "c4aa": c4aa, "c4fill": c4fill, "c3aa": c3aa}[key]()

@@ -169,32 +169,27 @@ def test_c4_full_size(hv, torch):
     _check_golden(full, "c4", edges, tiles, r, "c4-full")
 
 
-def test_c4_full_size_aa(hv, torch):
-    """Anti-aliased values (0-4) of the 2e8 edges' 4,096 requests, rendered in
-    one launch in the autotuned shape, as bench.py times them, against the
-    oracle's exact mode on the stored sample of 4 requests per zoom: equal
-    wherever no sub-sample is within 1e-6 px of r, and otherwise within the
-    bracket the ambiguous sub-samples allow."""
-    log("c4 aa full size: generate 2e8 edges")
-    edges = hvgen.gen_c4_edges()
-    tiles, r = hvgen.c4_requests(edges, n=4096)
-    g = np.load(os.path.join(GOLDEN, "fullsize_c4_aa.npz"))
-    fp = input_fingerprint(edges[::1000], edges.shape[0], tiles, r)
-    assert str(g["fingerprint"]) == fp, "the inputs differ from those the stored oracle values were made from"
+def _aa_golden(hv, torch, name, objs, kind, tiles, r, what):
+    """Anti-aliased values (0-4) of all requests, rendered in one launch in the
+    autotuned shape, as bench.py times them, against the oracle's exact mode
+    on the stored sample: equal wherever no sub-sample is within 1e-6 px of r,
+    and otherwise within the bracket the ambiguous sub-samples allow."""
+    g = np.load(os.path.join(GOLDEN, f"fullsize_{name}.npz"))
+    fp = input_fingerprint(objs[::1000], objs.shape[0], tiles, r)
+    assert str(g["fingerprint"]) == fp, f"{what}: the inputs differ from those the stored oracle values were made from"
     idx = g["idx"]
     assert np.array_equal(g["tiles"], tiles[idx]) and np.array_equal(g["r"], r[idx])
-    h = _build(hv, torch, edges, hv.HV_POLYGON_EDGES)
-    del edges
+    h = _build(hv, torch, objs, kind)
     reqs = hv.requests(h, tiles, r)
     scratch = torch.empty((len(tiles), 8192), dtype=torch.uint8, device="cuda")
     launch, _ = hv.hv_autotune(reqs, scratch)
     del scratch
-    log(f"c4 aa full size: tuned launch {launch}")
+    log(f"{what}: tuned launch {launch}")
     out = torch.empty((len(tiles), hv.HV_AA_BYTES), dtype=torch.uint8, device="cuda")
     out.fill_(0xA5)   # every value must be written
     hv.hv_render_batch_aa(reqs, out, launch)
     torch.cuda.synchronize()
-    got = out.cpu().numpy()[idx].reshape(-1, 256, 256)
+    got = out[torch.from_numpy(idx).cuda()].cpu().numpy().reshape(-1, 256, 256)
     del out
     torch.cuda.empty_cache()
     hv.hv_free(h)
@@ -205,13 +200,31 @@ def test_c4_full_size_aa(hv, torch):
     in_bracket = (got >= sure) & (got <= sure + amb)
     for z in np.unique(tiles[idx, 0]):
         sel = tiles[idx, 0] == z
-        log(f"c4 aa z{z}: {int(sel.sum())} tiles, nonzero={int((val[sel] > 0).sum())} "
+        log(f"{what} z{z}: {int(sel.sum())} tiles, nonzero={int((val[sel] > 0).sum())} "
             f"ambiguous sub-samples={int(amb[sel].sum())} mismatches={int(bad[sel].sum())}")
-    assert not bad.any(), f"c4 aa: {int(bad.sum())} values differ from the oracle"
-    assert in_bracket[~clean].all(), "c4 aa: a value outside its ambiguity bracket"
+    assert not bad.any(), f"{what}: {int(bad.sum())} values differ from the oracle"
+    assert in_bracket[~clean].all(), f"{what}: a value outside its ambiguity bracket"
     n_amb = int(amb.sum())
-    log(f"c4 aa: {len(idx)} sampled tiles, {4 * got.size} sub-samples, {n_amb} ambiguous")
-    assert n_amb <= AMBIGUOUS_LIMIT * 4 * got.size, f"c4 aa: {n_amb} ambiguous sub-samples"
+    log(f"{what}: {len(idx)} sampled tiles, {4 * got.size} sub-samples, {n_amb} ambiguous")
+    assert n_amb <= AMBIGUOUS_LIMIT * 4 * got.size, f"{what}: {n_amb} ambiguous sub-samples"
+
+
+def test_c4_full_size_aa(hv, torch):
+    """The 2e8 edges' 4,096 requests, anti-aliased, against 4 stored oracle
+    requests per zoom at zooms 2-20."""
+    log("c4 aa full size: generate 2e8 edges")
+    edges = hvgen.gen_c4_edges()
+    tiles, r = hvgen.c4_requests(edges, n=4096)
+    _aa_golden(hv, torch, "c4_aa", edges, hv.HV_POLYGON_EDGES, tiles, r, "c4 aa")
+
+
+def test_c3_full_size_aa(hv, torch):
+    """The 1e9 points' 10,000 requests, anti-aliased, against 4 stored oracle
+    requests per zoom at zooms 3-18."""
+    log("c3 aa full size: generate 1e9 points")
+    pts = hvgen.gen_c3_points(1_000_000_000)
+    tiles, r = hvgen.c3_requests(10_000)
+    _aa_golden(hv, torch, "c3_aa", pts, hv.HV_POINTS, tiles, r, "c3 aa")
 
 
 def _check_fill_sample(packed, edges, first, tiles, pick, what):
