@@ -764,15 +764,16 @@ int hv_autotune(const hv_request *sample, int64_t n, uint8_t *scratch_masks, hv_
     // The default's three shapes come first (queues at their minimum, 64 x
     // waves x objects per lane: larger queues cost occupancy); grid 2^20
     // gives each region its own workgroup, which helps batches whose regions
-    // differ widely in cost; a queue of 64 x waves (a leaf step's objects
-    // taken 64 x waves at a time) frees LDS for more workgroups per CU.
+    // differ widely in cost; a queue of 64 or 96 x waves (a leaf step's
+    // objects taken 64 x waves at a time) frees LDS for more workgroups per
+    // CU.
     // One wavefront per pixel block (region 0) is
     // not a candidate: it never won, and without the accept pass a single
     // run of it on a few dense low-zoom tiles can take seconds.
     static const hv_launch cands[] = {
         {0, 128, 1, 0, 32, 2, 0}, {0, 256, 2, 0, 32, 2, 0}, {0, 512, 4, 0, 32, 2, 0}, {0, 128, 1, 0, 32, 2, 128},
         {0, 128, 1, 0, 32, 2, 32}, {0, 512, 4, 0, 32, 2, 32}, {0, 128, 1, 1 << 20, 32, 2, 0},
-        {0, 64, 1, 1 << 20, 32, 2, 0}, {0, 64, 1, 0, 32, 2, 0},
+        {0, 96, 1, 1 << 20, 32, 2, 0}, {0, 64, 1, 1 << 20, 32, 2, 0}, {0, 96, 1, 0, 32, 2, 0}, {0, 64, 1, 0, 32, 2, 0},
         {0, 64, 1, 0, 32, 1}, {0, 256, 1, 0, 32, 4},
         {0, 128, 2, 0, 32, 1}, {0, 256, 4, 0, 32, 1}, {0, 128, 1, 0, 64, 2}, {0, 256, 2, 0, 64, 2},
         {0, 256, 4, 0, 64, 1}, {0, 512, 4, 0, 64, 2},
