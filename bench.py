@@ -103,14 +103,16 @@ def make_workload(key: str, scale: float = 1.0):
     raise KeyError(key)
 
 
-def query_kernel_name(launch) -> str:
-    """Name of the query kernel a launch shape runs (as profilers show it)."""
+def query_kernel_name(launch, aa: bool = False) -> str:
+    """Name of the query kernel a launch shape runs (as profilers show it);
+    aa: the anti-aliased kernel, always in region mode (region 32 when the
+    shape names none)."""
     if not launch:
-        return "k_query_region<32, 2, 0>"   # the default shape, whatever its waves per workgroup
+        return f"k_query_region<32, 2, {int(aa)}>"   # the default shape, whatever its waves per workgroup
     L = launch
-    region = L.get("region", 0)
+    region = L.get("region", 0) or (32 if aa else 0)
     if region:
-        return f"k_query_region<{region}, {L.get('objs_per_lane', 1) or 1}, 0>"
+        return f"k_query_region<{region}, {L.get('objs_per_lane', 1) or 1}, {int(aa)}>"
     return f"k_query<{L.get('block', 16) or 16}>"
 
 
@@ -204,6 +206,8 @@ def roofline_record(workload: str, launch, frontier_ms: float, query_ms: float, 
            "traffic_gbs": traffic / sec / 1e9 if traffic else None}
     if work.get("extrapolated"):
         rec["alg_extrapolated"] = work["extrapolated"]
+    if work.get("alg_bytes_upper_bound"):
+        rec["alg_bytes_note"] = "an upper bound: an object needed by two of a tile's four child tiles counts twice"
     if t_flops > t_bytes:
         rec.update({"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": tfl / FP64_PEAK_TFLOPS, "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS})
@@ -594,6 +598,10 @@ def main():
         aa_s = (time.perf_counter() - a0) / 5
         aa = {"tiles_per_s": n / aa_s, "ms_per_call": aa_s * 1e3,
               "note": "values 0-4 per pixel: how many of its four sub-samples (centre -+ 1/4 px in x and y) lie within r, in one pass"}
+        # the anti-aliased query kernel alone, HIP events on the stream it runs on
+        aa_frontier_ms, aa_query_ms = hv.hv_time_aa(reqs, out_aa, launch, reps=5)
+        aa["roofline"] = roofline_record(wl["name"] + "/aa", launch, aa_frontier_ms, aa_query_ms,
+                                         kernel=query_kernel_name(launch, aa=True))
         del out_aa
         stage(f"anti-aliased: {n / aa_s:.0f} tiles/s")
 

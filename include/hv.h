@@ -351,6 +351,13 @@ int hv_render_batch_noalloc(const hv_request *reqs, int64_t n, uint8_t *out_mask
 int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
                     double *ms);
 
+/* Kernel timing of anti-aliased batches, for their roofline: hv_time_kernels
+ * for hv_render_batch_aa (out_values as there; launch NULL takes that
+ * call's default shape).  ms[0] is the frontier kernel, ms[1] the
+ * anti-aliased query kernel.  Errors as hv_time_kernels. */
+int hv_time_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch, int32_t reps,
+               double *ms);
+
 /* Kernel timing of polygon filling, for its roofline: hv_render_fill's
  * arguments, rendered reps times, with HIP events on the calling thread's
  * stream around the tile-frontier kernel and the fill kernel.  ms (host, 2

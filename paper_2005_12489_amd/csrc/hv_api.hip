@@ -640,21 +640,28 @@ int hv_render_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     return HV_OK;
 }
 
+// The shape of an anti-aliased batch: one pass in region mode, four
+// sub-sample masks per region.
+int aa_shape(const hv_launch *launch, int max_levels, int64_t n, hv::LaunchShape *shape) {
+    int rc = resolve_shape(launch, max_levels, shape, n);
+    if (rc) return rc;
+    if (shape->region == 0) {
+        shape->region = 32;
+        if (!launch || !launch->cand_cap) shape->cand_cap = 64 * shape->waves * shape->opl;
+        if (shape->cand_cap < 64 * shape->waves * shape->opl) shape->cand_cap = 64 * shape->waves * shape->opl;
+    }
+    shape->aa = 1;
+    if (hv::query_lds_bytes(*shape, max_levels) > 65536)
+        return fail(HV_EINVAL, "launch shape needs more than 64 KiB of LDS per workgroup");
+    return HV_OK;
+}
+
 int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch) {
     BatchPlan p;
     int rc = plan_batch(reqs, n, &p);
     if (rc) return rc;
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, p.max_levels, &shape, n))) return rc;
-    // one pass in region mode: four sub-sample masks per region
-    if (shape.region == 0) {
-        shape.region = 32;
-        if (!launch || !launch->cand_cap) shape.cand_cap = 64 * shape.waves * shape.opl;
-        if (shape.cand_cap < 64 * shape.waves * shape.opl) shape.cand_cap = 64 * shape.waves * shape.opl;
-    }
-    shape.aa = 1;
-    if (hv::query_lds_bytes(shape, p.max_levels) > 65536)
-        return fail(HV_EINVAL, "launch shape needs more than 64 KiB of LDS per workgroup");
+    if ((rc = aa_shape(launch, p.max_levels, n, &shape))) return rc;
     if (n == 0) {
         t_err.clear();
         return HV_OK;
@@ -667,8 +674,9 @@ int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, c
     return HV_OK;
 }
 
-int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
-                    double *ms) {
+// Kernel timing of a batch (binary masks, or anti-aliased values with aa).
+int time_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
+               double *ms, bool aa, const char *who) {
     if (!ms) return fail(HV_EINVAL, "ms is NULL");
     if (reps < 1 || reps > 100000) return fail(HV_EINVAL, "reps must be in [1, 100000]");
     if (n <= 0) return fail(HV_EINVAL, "the batch is empty");
@@ -676,9 +684,10 @@ int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     int rc = plan_batch(reqs, n, &p);
     if (rc) return rc;
     hv_launch tuned;
-    if (!launch && tuned_for(reqs, n, &tuned)) launch = &tuned;
+    if (!aa && !launch && tuned_for(reqs, n, &tuned)) launch = &tuned;
     hv::LaunchShape shape;
-    if ((rc = resolve_shape(launch, p.max_levels, &shape, n))) return rc;
+    if ((rc = aa ? aa_shape(launch, p.max_levels, n, &shape) : resolve_shape(launch, p.max_levels, &shape, n)))
+        return rc;
     if ((rc = validate_out(out_masks))) return rc;
     hipEvent_t m[3] = {nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
@@ -686,7 +695,7 @@ int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     double sum[2] = {0.0, 0.0};
     for (int rep = 0; rep < reps && e == hipSuccess && rc == HV_OK; ++rep) {
         rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_masks, shape,
-                       "hv_time_kernels", m);
+                       who, m);
         if (rc) break;
         if ((e = hipEventSynchronize(m[2])) != hipSuccess) break;
         float a = 0, b = 0;
@@ -698,11 +707,21 @@ int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     for (int k = 0; k < 3; ++k)
         if (m[k]) (void)hipEventDestroy(m[k]);
     if (rc) return rc;
-    if (e != hipSuccess) return hip_status(e, "hv_time_kernels");
+    if (e != hipSuccess) return hip_status(e, who);
     ms[0] = sum[0] / reps;
     ms[1] = sum[1] / reps;
     t_err.clear();
     return HV_OK;
+}
+
+int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
+                    double *ms) {
+    return time_batch(reqs, n, out_masks, launch, reps, ms, false, "hv_time_kernels");
+}
+
+int hv_time_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch, int32_t reps,
+               double *ms) {
+    return time_batch(reqs, n, out_values, launch, reps, ms, true, "hv_time_aa");
 }
 
 int64_t hv_estimate_bytes(const hv_index *index, const hv_tile *tile, const hv_style *style) {

@@ -44,7 +44,7 @@ HV_NOALLOC_MAX_INDEXES = 16
 SYMBOLS = ("hv_index_build", "hv_render_tiles", "hv_render_tiles_ex", "hv_free", "hv_last_error",
            "hv_set_stream", "hv_index_info", "hv_index_read", "hv_render_batch", "hv_batcher_create",
            "hv_batcher_run", "hv_batcher_latency", "hv_batcher_free", "hv_autotune", "hv_tuned_launch",
-           "hv_time_kernels", "hv_time_fill", "hv_render_batch_aa", "hv_polygon_index_build", "hv_render_fill",
+           "hv_time_kernels", "hv_time_aa", "hv_time_fill", "hv_render_batch_aa", "hv_polygon_index_build", "hv_render_fill",
            "hv_render_batch_noalloc", "hv_estimate_bytes", "hv_estimate_batch_bytes")
 
 # hv_request as a numpy record (32 bytes, the C layout)
@@ -132,6 +132,9 @@ lib.hv_render_batch_aa.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_lau
 lib.hv_time_fill.restype = ctypes.c_int
 lib.hv_time_fill.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.c_int32,
                              ctypes.POINTER(ctypes.c_double)]
+lib.hv_time_aa.restype = ctypes.c_int
+lib.hv_time_aa.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.c_int32,
+                           ctypes.POINTER(ctypes.c_double)]
 lib.hv_time_kernels.restype = ctypes.c_int
 lib.hv_time_kernels.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(hv_launch), ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_double)]
@@ -326,6 +329,19 @@ def hv_render_fill(index: int, tiles, out_masks, launch=None) -> None:
     _sync_stream()
     _check(lib.hv_render_fill(index, t.ctypes.data_as(_P), t.shape[0], _device_ptr(out_masks),
                               ctypes.byref(L) if L else None))
+
+
+def hv_time_aa(reqs, out_values, launch=None, reps: int = 10):
+    """Mean (frontier kernel ms, anti-aliased query kernel ms) over reps
+    renders of the batch with hv_render_batch_aa, from HIP events on the
+    current stream."""
+    r = _reqs(reqs)
+    L = _launch(launch)
+    ms = (ctypes.c_double * 2)()
+    _sync_stream()
+    _check(lib.hv_time_aa(r.ctypes.data_as(_P), r.shape[0], _device_ptr(out_values),
+                          ctypes.byref(L) if L else None, int(reps), ms))
+    return ms[0], ms[1]
 
 
 def hv_time_fill(index: int, tiles, out_masks, launch=None, reps: int = 10):

@@ -122,6 +122,8 @@ def test_batch_validation_before_any_device_call(hv):
                                 (hv.requests(h, [(3, 1, 1)], 0.0), 1, "r_px")]:
             with pytest.raises(hv.HvError, match=msg):
                 hv.hv_time_kernels(reqs, 1, reps=reps)
+            with pytest.raises(hv.HvError, match=msg):
+                hv.hv_time_aa(reqs, 1, reps=reps)
         # fill timing: its own checks, then hv_render_fill's
         for index, tiles, reps, msg in [(0, [(3, 1, 1)], 0, "reps"), (0, [(3, 1, 1)], 100001, "reps"),
                                         (0, np.zeros((0, 3)), 1, "empty"), (0, [(3, 1, 1)], 1, "index is NULL"),

@@ -32,6 +32,9 @@ def test_query_kernel_names():
     assert b.query_kernel_name({"region": 32, "objs_per_lane": 0}) == "k_query_region<32, 1, 0>"
     assert b.query_kernel_name({"region": 0, "block": 8}) == "k_query<8>"
     assert b.query_kernel_name({"block": 0}) == "k_query<16>"
+    assert b.query_kernel_name(None, aa=True) == "k_query_region<32, 2, 1>"
+    assert b.query_kernel_name({"region": 0, "block": 16, "objs_per_lane": 2}, aa=True) == "k_query_region<32, 2, 1>"
+    assert b.query_kernel_name({"region": 64, "objs_per_lane": 1}, aa=True) == "k_query_region<64, 1, 1>"
     assert b.fill_kernel_name(None) == "k_fill_region<32>"
     assert b.fill_kernel_name({"region": 64, "waves_per_wg": 4}) == "k_fill_region<64>"
 
