@@ -597,11 +597,15 @@ def main():
         torch.cuda.synchronize()
         aa_s = (time.perf_counter() - a0) / 5
         aa = {"tiles_per_s": n / aa_s, "ms_per_call": aa_s * 1e3,
-              "note": "values 0-4 per pixel: how many of its four sub-samples (centre -+ 1/4 px in x and y) lie within r, in one pass"}
-        # the anti-aliased query kernel alone, HIP events on the stream it runs on
+              "note": "values 0-4 per pixel: how many of its four sub-samples (centre -+ 1/4 px in x and y) lie "
+                      "within r; requests on dense tiles (aa_split) render as their four child tiles at 2r, "
+                      "the rest in one pass"}
+        # the query kernels alone (child tiles, one pass), HIP events on the
+        # stream they run on
         aa_frontier_ms, aa_query_ms = hv.hv_time_aa(reqs, out_aa, launch, reps=5)
-        aa["roofline"] = roofline_record(wl["name"] + "/aa", launch, aa_frontier_ms, aa_query_ms,
-                                         kernel=query_kernel_name(launch, aa=True))
+        aa["roofline"] = roofline_record(
+            wl["name"] + "/aa", launch, aa_frontier_ms, aa_query_ms,
+            kernel=f"{query_kernel_name(launch)} (child tiles) + {query_kernel_name(launch, aa=True)} (one pass)")
         del out_aa
         stage(f"anti-aliased: {n / aa_s:.0f} tiles/s")
 

@@ -144,7 +144,17 @@ typedef struct {
     int32_t cull_nodes;     /* cull depth of the per-tile pass: it descends the tree while the next
                                level holds at most this many nodes that meet the tile, 1..256
                                (0 = 256); blocks and regions then walk on from those nodes */
+    int32_t aa_split;       /* anti-aliased output only (hv_render_batch_aa): which requests render
+                               as their four child tiles instead of in one pass.  k in [1, 62]: those
+                               whose index holds at least 2^k * 4^z objects; -1: none; -2: all;
+                               0: k = HV_AA_SPLIT_DEFAULT.  Only requests with z < HV_MAX_ZOOM and
+                               2 r <= HV_MAX_RADIUS qualify.  Other entry points ignore it. */
 } hv_launch;
+
+/* Default of hv_launch.aa_split: requests whose index holds at least
+ * 2^HV_AA_SPLIT_DEFAULT objects per tile of their zoom (as if spread
+ * evenly) render anti-aliased output as child tiles. */
+#define HV_AA_SPLIT_DEFAULT 12
 
 /* hv_render_tiles with an explicit launch shape (autotuning and variant
  * tests).  Every valid shape produces identical masks.  Extra HV_EINVAL
@@ -263,10 +273,24 @@ int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
  * reqs: host array as for hv_render_batch (0 <= z <= HV_MAX_ZOOM).
  * out_values: device, n * HV_AA_BYTES bytes, 16-byte aligned; the value of
  * pixel (i, j) of request k is at k * HV_AA_BYTES + j * 256 + i.
+ * A request can instead render as its four child tiles, (z + 1, 2x + a,
+ * 2y + b) for a, b in {0, 1}, in binary form at radius 2 r, each pixel's
+ * value then being the number of set bits among its 2 x 2 child pixels: the
+ * centres of those pixels are exactly its sub-samples, and doubling every
+ * length in pixels at the next zoom leaves each comparison unchanged, so
+ * both forms give the same values (up to rounding where a sub-sample's
+ * distance lies within rounding error of r).  The child form does four times the
+ * pixel work but none of the one-pass form's four-grid accepts; it is faster
+ * on dense tiles, where accepts decide most pixels.  launch->aa_split picks
+ * the requests that take it (default: HV_AA_SPLIT_DEFAULT).  A batch with
+ * such requests allocates 32 KiB of child masks per such request, plus
+ * 64 KiB per other request when both forms are present, in stream order
+ * on the calling thread's stream.
  * launch: the query shape (NULL = the default shape for n requests; a shape
  * with region = 0 runs with region 32, the one-pass form needing region
- * mode).  Asynchronous on the calling thread's stream.  Errors as
- * hv_render_batch; nothing is launched on error. */
+ * mode; the child tiles run in the shape as given).  Asynchronous on the
+ * calling thread's stream.  Errors as hv_render_batch, and HV_EINVAL for
+ * aa_split outside [-2, 62]; nothing is launched on error. */
 int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch);
 
 /* Polygon index for filling (Sec. 3.1, the multi-level index for polygons:
@@ -353,8 +377,10 @@ int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
 
 /* Kernel timing of anti-aliased batches, for their roofline: hv_time_kernels
  * for hv_render_batch_aa (out_values as there; launch NULL takes that
- * call's default shape).  ms[0] is the frontier kernel, ms[1] the
- * anti-aliased query kernel.  Errors as hv_time_kernels. */
+ * call's default shape).  ms[0] is the frontier kernel, ms[1] the query
+ * kernel: with requests in the child form (launch->aa_split), each is the
+ * sum over the two sub-batches (child tiles, one pass), and the small kernel
+ * that assembles the values is not counted.  Errors as hv_time_kernels. */
 int hv_time_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch, int32_t reps,
                double *ms);
 

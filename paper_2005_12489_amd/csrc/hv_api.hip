@@ -117,6 +117,7 @@ int resolve_shape(const hv_launch *l, int max_levels, hv::LaunchShape *s, int64_
     if (s->waves != 1 && s->waves != 2 && s->waves != 4)
         return fail(HV_EINVAL, "launch.waves_per_wg must be 1, 2 or 4");
     if (s->grid < 0 || s->grid > (1 << 20)) return fail(HV_EINVAL, "launch.grid_wgs must be in [0, 2^20]");
+    if (l && (l->aa_split < -2 || l->aa_split > 62)) return fail(HV_EINVAL, "launch.aa_split must be in [-2, 62]");
     if (hv::query_lds_bytes(*s, max_levels) > 65536)
         return fail(HV_EINVAL, "launch shape needs more than 64 KiB of LDS per workgroup");
     return HV_OK;
@@ -158,22 +159,26 @@ struct HostStage {
     }
 };
 thread_local HostStage t_stage;
+// the second sub-batch and the request map of an anti-aliased batch split
+// into child tiles and one-pass requests
+thread_local HostStage t_stage_b, t_stage_map;
 
 // Copies the staged workspace to a fresh stream-ordered device allocation
 // and launches the query; the allocation is released in stream order.
 int run_batch(const hv::DevIndex *ixs, int n_ix, int max_levels, const hv::DevReq *reqs, int64_t n_req,
-              uint8_t *out, const hv::LaunchShape &shape, const char *who, hipEvent_t *marks = nullptr) {
+              uint8_t *out, const hv::LaunchShape &shape, const char *who, hipEvent_t *marks = nullptr,
+              HostStage &st = t_stage) {
     const hv::Workspace w = hv::workspace_layout(n_req, n_ix);
-    hipError_t e = t_stage.acquire(w.staged_bytes());
+    hipError_t e = st.acquire(w.staged_bytes());
     if (e != hipSuccess) return hip_status(e, who);
-    hv::stage_host(w, ixs, n_ix, reqs, n_req, out, t_stage.p);
+    hv::stage_host(w, ixs, n_ix, reqs, n_req, out, st.p);
     unsigned char *dws = nullptr;
     e = hipMallocAsync((void **)&dws, w.total, t_stream);
     if (e != hipSuccess) return hip_status(e, who);
-    e = hipMemcpyAsync(dws, t_stage.p, w.staged_bytes(), hipMemcpyHostToDevice, t_stream);
-    if (e == hipSuccess) e = hipEventRecord(t_stage.ev, t_stream);
+    e = hipMemcpyAsync(dws, st.p, w.staged_bytes(), hipMemcpyHostToDevice, t_stream);
+    if (e == hipSuccess) e = hipEventRecord(st.ev, t_stream);
     if (e == hipSuccess) {
-        t_stage.pending = true;
+        st.pending = true;
         e = hv::launch_query(w, dws, max_levels, shape, t_stream, marks);
     }
     const hipError_t ef = hipFreeAsync(dws, t_stream);
@@ -446,6 +451,10 @@ hv_index *hv_polygon_index_build(const double *edges, int64_t n, const int64_t *
     return ix;
 }
 
+}  // extern "C"
+
+namespace {
+
 // Checks a fill call and resolves its shape; *empty is set for n_tiles = 0
 // (nothing to launch).
 int prepare_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
@@ -485,6 +494,10 @@ std::vector<hv::DevReq> fill_requests(const hv_tile *tiles, int64_t n_tiles) {
     for (int64_t k = 0; k < n_tiles; ++k) reqs[(size_t)k] = hv::DevReq{tiles[k].z, tiles[k].x, tiles[k].y, 0, 0.0};
     return reqs;
 }
+
+}  // namespace
+
+extern "C" {
 
 int hv_render_fill(const hv_index *index, const hv_tile *tiles, int64_t n_tiles, uint8_t *out_masks,
                    const hv_launch *launch) {
@@ -640,6 +653,10 @@ int hv_render_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const
     return HV_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
 // The shape of an anti-aliased batch: one pass in region mode, four
 // sub-sample masks per region.
 int aa_shape(const hv_launch *launch, int max_levels, int64_t n, hv::LaunchShape *shape) {
@@ -656,23 +673,108 @@ int aa_shape(const hv_launch *launch, int max_levels, int64_t n, hv::LaunchShape
     return HV_OK;
 }
 
+// An anti-aliased batch split by launch->aa_split: the requests rendered as
+// child tiles (map[k] = s >= 0: children 4s .. 4s + 3 of `kids`, child
+// (2x + a, 2y + b) at 4s + 2b + a, binary at 2r) and the others (map[k] =
+// -1 - s: request s of `whole`, one pass).
+struct AaPlan {
+    std::vector<hv::DevReq> kids, whole;
+    std::vector<int32_t> map;
+};
+
+bool aa_by_children(const hv_index *ix, const hv::DevReq &q, int split) {
+    if (split == -1 || q.z >= HV_MAX_ZOOM || 2.0 * q.r > HV_MAX_RADIUS) return false;
+    if (split == -2) return true;
+    const int k = split ? split : HV_AA_SPLIT_DEFAULT;
+    return (double)ix->a.n >= std::ldexp(1.0, k + 2 * q.z);
+}
+
+void plan_aa(const BatchPlan &p, int split, AaPlan *a) {
+    const int64_t n = (int64_t)p.reqs.size();
+    a->map.resize((size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+        const hv::DevReq &q = p.reqs[(size_t)k];
+        if (aa_by_children(p.owners[(size_t)q.index], q, split)) {
+            a->map[(size_t)k] = (int32_t)(a->kids.size() / 4);
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c)
+                    a->kids.push_back(hv::DevReq{q.z + 1, 2 * q.x + c, 2 * q.y + b, q.index, 2.0 * q.r});
+        } else {
+            a->map[(size_t)k] = -1 - (int32_t)a->whole.size();
+            a->whole.push_back(q);
+        }
+    }
+}
+
+// Renders an anti-aliased batch: one pass (shape sa) for every request, or,
+// with requests in the child form, their child tiles in binary form (shape
+// sb) and the one-pass rest into stream-ordered scratch, then the values
+// assembled into out.  marks: six events (child tiles, then one pass; see
+// run_batch) or NULL.
+int run_aa(const BatchPlan &p, int64_t n, uint8_t *out, const hv::LaunchShape &sa, const hv::LaunchShape &sb,
+           int split, const char *who, hipEvent_t *marks = nullptr) {
+    AaPlan a;
+    plan_aa(p, split, &a);
+    const int n_ix = (int)p.table.size();
+    if (a.kids.empty())
+        return run_batch(p.table.data(), n_ix, p.max_levels, p.reqs.data(), n, out, sa, who,
+                         marks ? marks + 3 : nullptr);
+    const size_t nw = a.whole.size();
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t kid_bytes = a.kids.size() * (size_t)HV_MASK_BYTES, whole_bytes = nw * (size_t)HV_AA_BYTES;
+    const size_t map_bytes = (size_t)n * sizeof(int32_t);
+    uint8_t *tmp = nullptr;
+    hipError_t e = t_stage_map.acquire(map_bytes);
+    if (e != hipSuccess) return hip_status(e, who);
+    std::memcpy(t_stage_map.p, a.map.data(), map_bytes);
+    if ((e = hipMallocAsync((void **)&tmp, up(kid_bytes) + up(whole_bytes) + map_bytes, t_stream)) != hipSuccess)
+        return hip_status(e, who);
+    uint8_t *kids = tmp, *whole = tmp + up(kid_bytes);
+    int32_t *map = reinterpret_cast<int32_t *>(tmp + up(kid_bytes) + up(whole_bytes));
+    int rc = HV_OK;
+    e = hipMemcpyAsync(map, t_stage_map.p, map_bytes, hipMemcpyHostToDevice, t_stream);
+    if (e == hipSuccess) e = hipEventRecord(t_stage_map.ev, t_stream);
+    if (e == hipSuccess) {
+        t_stage_map.pending = true;
+        rc = run_batch(p.table.data(), n_ix, p.max_levels, a.kids.data(), (int64_t)a.kids.size(), kids, sb, who,
+                       marks);
+        if (!rc && nw)
+            rc = run_batch(p.table.data(), n_ix, p.max_levels, a.whole.data(), (int64_t)nw, whole, sa, who,
+                           marks ? marks + 3 : nullptr, t_stage_b);
+        if (!rc) e = hv::launch_aa_assemble(map, n, kids, whole, out, t_stream);
+    }
+    const hipError_t ef = hipFreeAsync(tmp, t_stream);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_status(e, who);
+    if (ef != hipSuccess) return hip_status(ef, who);
+    return HV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch) {
     BatchPlan p;
     int rc = plan_batch(reqs, n, &p);
     if (rc) return rc;
-    hv::LaunchShape shape;
-    if ((rc = aa_shape(launch, p.max_levels, n, &shape))) return rc;
+    hv::LaunchShape sa, sb;
+    if ((rc = aa_shape(launch, p.max_levels, n, &sa))) return rc;
+    if ((rc = resolve_shape(launch, p.max_levels, &sb, 4 * n))) return rc;
     if (n == 0) {
         t_err.clear();
         return HV_OK;
     }
     if ((rc = validate_out(out_values))) return rc;
-    rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_values, shape,
-                   "hv_render_batch_aa");
+    rc = run_aa(p, n, out_values, sa, sb, launch ? launch->aa_split : 0, "hv_render_batch_aa");
     if (rc) return rc;
     t_err.clear();
     return HV_OK;
 }
+
+}  // extern "C"
+
+namespace {
 
 // Kernel timing of a batch (binary masks, or anti-aliased values with aa).
 int time_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
@@ -685,26 +787,36 @@ int time_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_l
     if (rc) return rc;
     hv_launch tuned;
     if (!aa && !launch && tuned_for(reqs, n, &tuned)) launch = &tuned;
-    hv::LaunchShape shape;
+    hv::LaunchShape shape, sb;
     if ((rc = aa ? aa_shape(launch, p.max_levels, n, &shape) : resolve_shape(launch, p.max_levels, &shape, n)))
         return rc;
+    if (aa && (rc = resolve_shape(launch, p.max_levels, &sb, 4 * n))) return rc;
     if ((rc = validate_out(out_masks))) return rc;
-    hipEvent_t m[3] = {nullptr, nullptr, nullptr};
+    // six marks: around the frontier and query kernels of the child tiles,
+    // then of the one-pass requests (binary batches use the second three)
+    hipEvent_t m[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&m[k]);
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) e = hipEventCreate(&m[k]);
     double sum[2] = {0.0, 0.0};
     for (int rep = 0; rep < reps && e == hipSuccess && rc == HV_OK; ++rep) {
-        rc = run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_masks, shape,
-                       who, m);
+        // a mark no kernel follows in this call stays unrecorded: record all
+        // six first, so that unused pairs time zero
+        for (int k = 0; k < 6 && e == hipSuccess; ++k) e = hipEventRecord(m[k], t_stream);
+        if (e != hipSuccess) break;
+        rc = aa ? run_aa(p, n, out_masks, shape, sb, launch ? launch->aa_split : 0, who, m)
+                : run_batch(p.table.data(), (int)p.table.size(), p.max_levels, p.reqs.data(), n, out_masks, shape,
+                            who, m + 3);
         if (rc) break;
-        if ((e = hipEventSynchronize(m[2])) != hipSuccess) break;
-        float a = 0, b = 0;
-        if ((e = hipEventElapsedTime(&a, m[0], m[1])) != hipSuccess) break;
-        if ((e = hipEventElapsedTime(&b, m[1], m[2])) != hipSuccess) break;
-        sum[0] += a;
-        sum[1] += b;
+        if ((e = hipStreamSynchronize(t_stream)) != hipSuccess) break;
+        for (int s = 0; s < 2 && e == hipSuccess; ++s) {
+            float a = 0, b = 0;
+            if ((e = hipEventElapsedTime(&a, m[3 * s], m[3 * s + 1])) != hipSuccess) break;
+            if ((e = hipEventElapsedTime(&b, m[3 * s + 1], m[3 * s + 2])) != hipSuccess) break;
+            sum[0] += a;
+            sum[1] += b;
+        }
     }
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 6; ++k)
         if (m[k]) (void)hipEventDestroy(m[k]);
     if (rc) return rc;
     if (e != hipSuccess) return hip_status(e, who);
@@ -713,6 +825,10 @@ int time_batch(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_l
     t_err.clear();
     return HV_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int hv_time_kernels(const hv_request *reqs, int64_t n, uint8_t *out_masks, const hv_launch *launch, int32_t reps,
                     double *ms) {

@@ -158,6 +158,14 @@ hipError_t launch_query(const Workspace &w, unsigned char *dws, int max_levels, 
 // Workgroups that fill the current device for a shape (occupancy x CUs).
 int persistent_grid(const LaunchShape &s, int max_levels);
 
+// Anti-aliased values of n requests (HV_AA_BYTES each at out) from child
+// masks or one-pass values: map[k] >= 0 takes the 2 x 2 bit counts of the
+// four 8192-byte masks at kids + 4 map[k] * 8192 (child (2x + a, 2y + b)
+// at index 2b + a), map[k] < 0 copies request -1 - map[k] of `whole`.  map,
+// kids, whole and out are device memory.
+hipError_t launch_aa_assemble(const int32_t *map, int64_t n, const uint8_t *kids, const uint8_t *whole,
+                              uint8_t *out, hipStream_t stream);
+
 }  // namespace hv
 
 // An index as the C ABI hands it out.

@@ -63,7 +63,8 @@ class hv_style(ctypes.Structure):
 class hv_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
                 ("waves_per_wg", ctypes.c_int32), ("grid_wgs", ctypes.c_int32), ("region", ctypes.c_int32),
-                ("objs_per_lane", ctypes.c_int32), ("cull_nodes", ctypes.c_int32)]
+                ("objs_per_lane", ctypes.c_int32), ("cull_nodes", ctypes.c_int32),
+                ("aa_split", ctypes.c_int32)]
 
 
 class hv_info(ctypes.Structure):

@@ -50,9 +50,11 @@ int main() {
     CHECK(hv_render_tiles(e, ok_tiles, 2, &st, host.data() ? reinterpret_cast<uint8_t *>(host.data()) : dummy) ==
           HV_EINVAL);                                                      // host output
     hv_launch L{};
-    const int bad_fields[][7] = {{12, 0, 0, 0, 0, 0, 0}, {0, 32, 0, 0, 0, 0, 0}, {0, 5000, 0, 0, 0, 0, 0},
-                                 {0, 0, 3, 0, 0, 0, 0},  {0, 0, 0, -1, 0, 0, 0}, {0, 0, 0, 0, 16, 0, 0},
-                                 {0, 0, 0, 0, 32, 3, 0}, {0, 0, 0, 0, 0, 0, 300}, {0, 64, 4, 0, 64, 4, 0}};
+    static_assert(sizeof(hv_launch) == 8 * sizeof(int), "hv_launch is eight int32 fields");
+    const int bad_fields[][8] = {{12, 0, 0, 0, 0, 0, 0, 0}, {0, 32, 0, 0, 0, 0, 0, 0}, {0, 5000, 0, 0, 0, 0, 0, 0},
+                                 {0, 0, 3, 0, 0, 0, 0, 0},  {0, 0, 0, -1, 0, 0, 0, 0}, {0, 0, 0, 0, 16, 0, 0, 0},
+                                 {0, 0, 0, 0, 32, 3, 0, 0}, {0, 0, 0, 0, 0, 0, 300, 0}, {0, 64, 4, 0, 64, 4, 0, 0},
+                                 {0, 0, 0, 0, 0, 0, 0, -3}, {0, 0, 0, 0, 0, 0, 0, 63}};
     for (const auto &f : bad_fields) {
         std::memcpy(&L, f, sizeof L);
         CHECK(hv_render_tiles_ex(e, ok_tiles, 1, &st, dummy, &L) == HV_EINVAL);

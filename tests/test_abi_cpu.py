@@ -31,6 +31,9 @@ def test_every_declared_symbol_is_exported(hv):
     exported = set(re.findall(r"\bT (hv_[a-z_]+)\b", out))
     missing = [n for n in names if n not in exported]
     assert not missing, missing
+    # and no internal helper leaks out with C linkage
+    c_names = set(re.findall(r"\bT ([A-Za-z][A-Za-z0-9_]*)$", out, re.M))
+    assert c_names == set(names), sorted(c_names ^ set(names))
     assert set(hv.SYMBOLS) == set(names), sorted(set(names) ^ set(hv.SYMBOLS))
 
 
@@ -115,6 +118,9 @@ def test_batch_validation_before_any_device_call(hv):
                 hv.hv_render_batch_aa(reqs, 1)
         with pytest.raises(hv.HvError, match="NULL"):
             hv.hv_render_batch_aa(hv.requests(h, [(3, 1, 1)], 1.0), 0)
+        for split in (-3, 63):
+            with pytest.raises(hv.HvError, match="aa_split"):
+                hv.hv_render_batch_aa(hv.requests(h, [(3, 1, 1)], 1.0), 1, {"aa_split": split})
         hv.hv_render_batch_aa(hv.requests(h, np.zeros((0, 3)), 1.0), 0)     # empty batch
         for reqs, reps, msg in [(hv.requests(h, np.zeros((0, 3)), 1.0), 1, "empty"),
                                 (hv.requests(h, [(3, 1, 1)], 1.0), 0, "reps"),

@@ -94,8 +94,12 @@ def test_aa_points_mixed_zooms_and_radii(hv, torch):
     log("aa clustered points, zooms 0-18")
     h = build(hv, torch, pts, hv.HV_POINTS)
     ix = oracle.OracleIndex(pts, oracle.POINTS)
-    got = render_aa(hv, torch, h, tiles, rr)
-    check_aa(got, ix.render_aa(tiles, rr), "aa clustered points")
+    ref = ix.render_aa(tiles, rr)
+    # the default split (zooms 0-1 as child tiles here), every request as
+    # child tiles, and none
+    for split in (0, -2, -1):
+        got = render_aa(hv, torch, h, tiles, rr, launch={"region": 32, "objs_per_lane": 2, "aa_split": split})
+        check_aa(got, ref, f"aa clustered points, aa_split {split}")
     hv.hv_free(h)
 
 
@@ -115,9 +119,14 @@ def test_aa_mixed_batch_and_extremes(hv, torch):
     tiles = np.array([c[1] for c in cases])
     rs = np.array([c[2] for c in cases])
     log("aa mixed batch over two indexes")
-    got = render_aa(hv, torch, np.array(hs, dtype=np.uint64)[ds], tiles, rs)
-    for d in (0, 1):
-        sel = np.nonzero(ds == d)[0]
-        check_aa(got[sel], ixs[d].render_aa(tiles[sel], rs[sel]), f"aa mixed dataset {d}")
+    refs = [ixs[d].render_aa(tiles[ds == d], rs[ds == d]) for d in (0, 1)]
+    # with aa_split -2, the zoom-22 and r = 64 requests stay in one pass; the
+    # last launch renders child tiles one wavefront per pixel block
+    for L in ({"region": 32, "objs_per_lane": 2}, {"region": 32, "objs_per_lane": 2, "aa_split": -2},
+              {"region": 32, "aa_split": -1}, {"aa_split": 1}):
+        split = L.get("aa_split", 0)
+        got = render_aa(hv, torch, np.array(hs, dtype=np.uint64)[ds], tiles, rs, launch=L)
+        for d in (0, 1):
+            check_aa(got[ds == d], refs[d], f"aa mixed dataset {d}, aa_split {split}")
     for h in hs:
         hv.hv_free(h)
