@@ -123,6 +123,7 @@ struct DevBatch {
     BatchHeader *hdr;
     const DevIndex *ixs;
     const DevReq *reqs;
+    const uint32_t *order;  // the requests by zoom, lowest first: the tile-frontier kernel's order
     uint32_t *frontier;  // per request: up to 256 frontier nodes
     int32_t *fmeta;      // per request: frontier size, frontier level, 64 bits of regions it reaches
     uint32_t *list;      // compacted list of requests with data nearby
@@ -136,12 +137,16 @@ struct DevBatch {
 // from the host; the rest is written by the kernels.
 struct Workspace {
     int64_t n_req;
-    size_t hdr_off, table_off, req_off, frontier_off, fmeta_off, list_off, elist_off, done_off, ts_off, total;
+    size_t hdr_off, table_off, req_off, order_off, frontier_off, fmeta_off, list_off, elist_off, done_off, ts_off,
+        total;
     size_t staged_bytes() const { return frontier_off; }
 };
 Workspace workspace_layout(int64_t n_req, int n_ix);
 
-// Fills the host part of a workspace.
+// Fills the host part of a workspace: header, index table, requests, and
+// their order by zoom (lowest first, stable), in which the tile-frontier
+// kernel lists them for the query kernel, so that dense low-zoom tiles start
+// first and the short high-zoom ones fill the end of the launch.
 void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq *reqs, int64_t n_req, uint8_t *out,
                 unsigned char *host);
 

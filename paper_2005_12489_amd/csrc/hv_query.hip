@@ -30,6 +30,7 @@
 // children at once; hits are pushed with one ballot.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -104,8 +105,9 @@ __global__ __launch_bounds__(256) void k_tile_frontier(DevBatch B, int rs, int c
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps per-tile values scalar
     if (blockIdx.x == 0 && threadIdx.x == 0) B.hdr->t_start = wall_clock64();
-    const int64_t t = (int64_t)blockIdx.x * 4 + wv;
-    if (t >= B.hdr->n_req) return;
+    const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+    if (i >= B.hdr->n_req) return;
+    const int64_t t = B.order[i];  // requests by zoom, lowest first: the list follows this order
     const DevReq rq = B.reqs[t];
     const DevIndex ix = B.ixs[rq.index];
     const double iS = ldexp(1.0, -8 - rq.z), S = ldexp(256.0, rq.z);
@@ -1606,7 +1608,8 @@ Workspace workspace_layout(int64_t n_req, int n_ix) {
     w.hdr_off = 0;
     w.table_off = 256;
     w.req_off = w.table_off + align256(sizeof(DevIndex) * (size_t)n_ix);
-    w.frontier_off = w.req_off + align256(sizeof(DevReq) * (size_t)n_req);
+    w.order_off = w.req_off + align256(sizeof(DevReq) * (size_t)n_req);
+    w.frontier_off = w.order_off + align256(sizeof(uint32_t) * (size_t)n_req);
     w.fmeta_off = w.frontier_off + align256(sizeof(uint32_t) * kFrontier * (size_t)n_req);
     w.list_off = w.fmeta_off + align256(sizeof(int32_t) * 4 * (size_t)n_req);
     w.elist_off = w.list_off + align256(sizeof(uint32_t) * (size_t)n_req);
@@ -1625,6 +1628,14 @@ void stage_host(const Workspace &w, const DevIndex *ixs, int n_ix, const DevReq 
     memcpy(host + w.hdr_off, &h, sizeof h);
     memcpy(host + w.table_off, ixs, sizeof(DevIndex) * (size_t)n_ix);
     memcpy(host + w.req_off, reqs, sizeof(DevReq) * (size_t)n_req);
+    // counting sort by zoom, stable (zooms are validated; the clamp only
+    // keeps the buckets in bounds)
+    auto bucket = [&](int64_t k) { return std::min(std::max(reqs[k].z, 0), (int32_t)HV_MAX_ZOOM); };
+    int64_t start[HV_MAX_ZOOM + 2] = {};
+    for (int64_t k = 0; k < n_req; ++k) ++start[bucket(k) + 1];
+    for (int z = 0; z <= HV_MAX_ZOOM; ++z) start[z + 1] += start[z];
+    uint32_t *order = reinterpret_cast<uint32_t *>(host + w.order_off);
+    for (int64_t k = 0; k < n_req; ++k) order[start[bucket(k)]++] = (uint32_t)k;
 }
 
 DevBatch device_batch(const Workspace &w, unsigned char *dws) {
@@ -1632,6 +1643,7 @@ DevBatch device_batch(const Workspace &w, unsigned char *dws) {
     b.hdr = reinterpret_cast<BatchHeader *>(dws + w.hdr_off);
     b.ixs = reinterpret_cast<const DevIndex *>(dws + w.table_off);
     b.reqs = reinterpret_cast<const DevReq *>(dws + w.req_off);
+    b.order = reinterpret_cast<const uint32_t *>(dws + w.order_off);
     b.frontier = reinterpret_cast<uint32_t *>(dws + w.frontier_off);
     b.fmeta = reinterpret_cast<int32_t *>(dws + w.fmeta_off);
     b.list = reinterpret_cast<uint32_t *>(dws + w.list_off);
