@@ -333,9 +333,9 @@ def hv_render_fill(index: int, tiles, out_masks, launch=None) -> None:
 
 
 def hv_time_aa(reqs, out_values, launch=None, reps: int = 10):
-    """Mean (frontier kernel ms, anti-aliased query kernel ms) over reps
-    renders of the batch with hv_render_batch_aa, from HIP events on the
-    current stream."""
+    """Mean (frontier kernel ms, query kernel ms) over reps renders of the
+    batch with hv_render_batch_aa, from HIP events on the current stream;
+    with child-tile requests each is the sum over the two sub-batches."""
     r = _reqs(reqs)
     L = _launch(launch)
     ms = (ctypes.c_double * 2)()

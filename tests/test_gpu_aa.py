@@ -98,8 +98,15 @@ def test_aa_points_mixed_zooms_and_radii(hv, torch):
     # the default split (zooms 0-1 as child tiles here), every request as
     # child tiles, and none
     for split in (0, -2, -1):
-        got = render_aa(hv, torch, h, tiles, rr, launch={"region": 32, "objs_per_lane": 2, "aa_split": split})
+        L = {"region": 32, "objs_per_lane": 2, "aa_split": split}
+        got = render_aa(hv, torch, h, tiles, rr, launch=L)
         check_aa(got, ref, f"aa clustered points, aa_split {split}")
+        # the timing entry point renders the same values, with positive times
+        out = torch.zeros((len(tiles), hv.HV_AA_BYTES), dtype=torch.uint8, device="cuda")
+        ms = hv.hv_time_aa(hv.requests(h, tiles, rr), out, L, reps=2)
+        torch.cuda.synchronize()
+        assert ms[0] > 0 and ms[1] > 0, ms
+        assert np.array_equal(out.cpu().numpy().reshape(-1, 256, 256), got), split
     hv.hv_free(h)
 
 
