@@ -267,9 +267,10 @@ int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
  * printed measures all four against the object nearest the centre, which
  * can count fewer).  One pass of the region kernel, with four sub-sample
  * masks per region: it culls with the samples' reach (r + 1/4 px per axis),
- * lights whole pixels whose centre lies within r - sqrt(2)/4 px of an object
- * (Algorithm 1's R1) without reading objects, and tests the four sub-samples
- * of every other pixel in reach exactly (FP64, inclusive).
+ * and from r = 1 px on sets all four sub-samples of a pixel whose centre lies
+ * within r - sqrt(2)/4 px of an object (Algorithm 1's R1) and none of one
+ * beyond r + sqrt(2)/4 (R2); it tests the four sub-samples of every other
+ * pixel in reach exactly (FP64, inclusive).
  * reqs: host array as for hv_render_batch (0 <= z <= HV_MAX_ZOOM).
  * out_values: device, n * HV_AA_BYTES bytes, 16-byte aligned; the value of
  * pixel (i, j) of request k is at k * HV_AA_BYTES + j * 256 + i.
@@ -288,7 +289,8 @@ int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
  * on the calling thread's stream.
  * launch: the query shape (NULL = the default shape for n requests; a shape
  * with region = 0 runs with region 32, the one-pass form needing region
- * mode; the child tiles run in the shape as given).  Asynchronous on the
+ * mode; the child tiles run in the shape as given, or with NULL in the
+ * default shape for their number).  Asynchronous on the
  * calling thread's stream.  Errors as hv_render_batch, and HV_EINVAL for
  * aa_split outside [-2, 62]; nothing is launched on error. */
 int hv_render_batch_aa(const hv_request *reqs, int64_t n, uint8_t *out_values, const hv_launch *launch);
