@@ -267,7 +267,9 @@ int hv_tuned_launch(const hv_request *reqs, int64_t n, hv_launch *out);
  * printed measures all four against the object nearest the centre, which
  * can count fewer).  One pass of the region kernel, with four sub-sample
  * masks per region: it culls with the samples' reach (r + 1/4 px per axis),
- * and from r = 1 px on sets all four sub-samples of a pixel whose centre lies
+ * lights sub-samples near node boxes and representatives on each sub-sample
+ * grid without reading objects (the binary kernel's accepts), and from
+ * r = 1 px on sets all four sub-samples of a pixel whose centre lies
  * within r - sqrt(2)/4 px of an object (Algorithm 1's R1) and none of one
  * beyond r + sqrt(2)/4 (R2); it tests the four sub-samples of every other
  * pixel in reach exactly (FP64, inclusive).
