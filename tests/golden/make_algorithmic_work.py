@@ -16,9 +16,9 @@ brute force of N_box and N_unlit_cand).  Per-zoom sums are kept beside the
 totals.
 
 Calls only the oracle and the seeded generators.  Usage:
-    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4] [c3] [c4fill] [c4aa]
+    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4] [c3] [c4fill] [c1aa] [c2aa] [c4aa]
 (c3: sampled and extrapolated per zoom, see c3_sampled; c4fill: the fill
-counters, see c4fill).
+counters, see c4fill; c<k>aa: anti-aliased output of c<k>, see aa_counts).
 """
 from __future__ import annotations
 
@@ -160,30 +160,32 @@ def c4fill(data):
     print(name, {k: v for k, v in rec.items() if k != "per_zoom"}, f"{time.time() - t0:.1f}s", flush=True)
 
 
-def c4aa(data):
-    """Anti-aliased output of the 2e8 edges' 4,096 requests (Algorithm 1's
-    0-4 per pixel).  A pixel's four sub-samples (centre -+ 1/4 px) are the
-    pixel centres of its four children one zoom deeper, and r px at zoom z is
-    2r px there, so the oracle's counters of the 16,384 child tiles at 2r
-    count the sub-samples' work:
-      bytes = 65536 per tile (one byte per pixel) + 32 * N_unlit_cand summed
-              over the four children (an object needed by two children counts
-              twice: an upper bound);
-      flops = 18 per (unlit sub-sample, box-meeting edge) pair + one witness
-              test per lit sub-sample, summed over the children (exact)."""
-    name = "polygon-edges-2e8-4096mixed-z2-20-w1-5"
+def aa_counts(data, key):
+    """Anti-aliased output of a workload's requests (Algorithm 1's 0-4 per
+    pixel).  A pixel's four sub-samples (centre -+ 1/4 px) are the pixel
+    centres of its four children one zoom deeper, and r px at zoom z is 2r px
+    there, so the oracle's counters of the child tiles at 2r count the
+    sub-samples' work:
+      bytes = 65536 per tile (one byte per pixel) + s_obj * N_unlit_cand
+              summed over the four children (an object needed by two children
+              counts twice: an upper bound);
+      flops = f per (unlit sub-sample, box-meeting object) pair + one witness
+              test per lit sub-sample, summed over the children (exact);
+    with s_obj and f as for the binary masks (16 B and 6 for points, 32 B and
+    18 for segments and edges)."""
     t0 = time.time()
-    edges = hvgen.gen_c4_edges()
-    tiles, r = hvgen.c4_requests(edges, n=4096)
+    name, objs, kind, tiles, r = workload(key)
     n = len(tiles)
     kids = np.empty((4 * n, 3), dtype=np.int64)
     for k, (a, b) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
         kids[k::4] = np.stack([tiles[:, 0] + 1, 2 * tiles[:, 1] + a, 2 * tiles[:, 2] + b], 1)
     rk = np.repeat(2.0 * np.asarray(r, dtype=np.float64), 4)
-    ix = oracle.OracleIndex(edges, oracle.POLYGON_EDGES)
+    ix = oracle.OracleIndex(objs, kind)
     n_obj = int(ix.n)
-    del edges
+    del objs
     print(f"{name}/aa: oracle index built, {time.time() - t0:.1f}s", flush=True)
+    s_obj = 16 if kind == oracle.POINTS else 32
+    f = 6 if kind == oracle.POINTS else 18
     cnt = np.zeros((4 * n, 5), dtype=np.int64)
     for s in range(0, 4 * n, 256):
         cnt[s:s + 256] = ix.render(kids[s:s + 256], rk[s:s + 256], want_bit=False, want_counters=True)["counters"]
@@ -194,18 +196,19 @@ def c4aa(data):
         sel = tiles[:, 0] == z
         cz = per[sel].sum(0)
         zooms[str(int(z))] = {"tiles": int(sel.sum()),
-                              "alg_bytes": int(65536 * sel.sum() + 32 * cz[oracle.C_UNLIT_CAND]),
-                              "alg_flops": int(18 * (cz[oracle.C_NBOX_UNLIT] + cz[oracle.C_LIT]))}
+                              "alg_bytes": int(65536 * sel.sum() + s_obj * cz[oracle.C_UNLIT_CAND]),
+                              "alg_flops": int(f * (cz[oracle.C_NBOX_UNLIT] + cz[oracle.C_LIT]))}
     c = per.sum(0)
     data[name + "/aa"] = {
         "tiles": n, "objects": n_obj, "lit_subsamples": int(c[oracle.C_LIT]),
         "ambiguous_subsamples": int(c[oracle.C_AMB]),
-        "alg_bytes": int(65536 * n + 32 * c[oracle.C_UNLIT_CAND]),
-        "alg_flops": int(18 * (c[oracle.C_NBOX_UNLIT] + c[oracle.C_LIT])),
+        "alg_bytes": int(65536 * n + s_obj * c[oracle.C_UNLIT_CAND]),
+        "alg_flops": int(f * (c[oracle.C_NBOX_UNLIT] + c[oracle.C_LIT])),
         "alg_bytes_upper_bound": True, "per_zoom": zooms,
-        "note": "sub-samples = pixel centres of the four children one zoom deeper at 2r: bytes = 65536 per tile + "
-                "32 per edge needed to certify an unlit sub-sample, summed over the children (an upper bound); "
-                "flops = 18 per (unlit sub-sample, box-meeting edge) pair + one witness test per lit sub-sample"}
+        "note": f"sub-samples = pixel centres of the four children one zoom deeper at 2r: bytes = 65536 per tile + "
+                f"{s_obj} per object needed to certify an unlit sub-sample, summed over the children (an upper "
+                f"bound); flops = {f} per (unlit sub-sample, box-meeting object) pair + one witness test per lit "
+                f"sub-sample"}
     print(name + "/aa", {k: v for k, v in data[name + "/aa"].items() if k != "per_zoom"},
           f"{time.time() - t0:.1f}s", flush=True)
 
@@ -217,9 +220,9 @@ def main(keys):
         c3_sampled(data)
         with open(OUT, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
-    if "c4aa" in keys:
-        keys = [k for k in keys if k != "c4aa"]
-        c4aa(data)
+    for key in [k for k in keys if k.endswith("aa")]:
+        keys = [k for k in keys if k != key]
+        aa_counts(data, key[:-2])
         with open(OUT, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
     if "c4fill" in keys:
