@@ -137,3 +137,22 @@ def test_aa_mixed_batch_and_extremes(hv, torch):
             check_aa(got[ds == d], refs[d], f"aa mixed dataset {d}, aa_split {split}")
     for h in hs:
         hv.hv_free(h)
+
+
+def test_aa_c2_full_size_all_tiles(hv, torch):
+    """The full 10M-segment workload, anti-aliased: all 4096 zoom-6 tiles in one
+    call (one pass: 10M segments are below the default split at zoom 6),
+    each against the oracle's exact mode; the ambiguous sub-samples are
+    counted over all 1.07e9 of them."""
+    segs = hvgen.gen_c2_segments()
+    tiles, r = hvgen.c2_requests()
+    log("aa c2-full build")
+    h = build(hv, torch, segs, hv.HV_SEGMENTS)
+    log("aa c2-full render 4096 tiles")
+    got = render_aa(hv, torch, h, tiles, r)
+    hv.hv_free(h)
+    log("aa c2-full oracle on all 4096 tiles")
+    ref = oracle.OracleIndex(segs, oracle.SEGMENTS).render_aa(tiles, r)
+    del segs
+    check_aa(got, ref, "aa c2-full")
+    assert (got > 0).sum() > 0
