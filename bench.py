@@ -159,8 +159,9 @@ def algorithmic_work(workload: str, zooms=None):
     large for the oracle to count whole has an entry counted on a per-zoom
     sample and extrapolated per zoom ("<workload>/zooms-A-B-extrapolated");
     its requests at zooms the entry does not cover (`zooms`: the zoom of each
-    request) add their 8192 mask bytes and nothing else, so the figure is a
-    lower bound, and the record says so."""
+    request) add their output bytes (8192 per mask, or the entry's
+    mask_bytes) and nothing else, so the figure is a lower bound, and the
+    record says so."""
     if not os.path.exists(WORK_FILE):
         return None
     data = json.load(open(WORK_FILE))
@@ -174,7 +175,8 @@ def algorithmic_work(workload: str, zooms=None):
     covered = np.isin(zs, [int(z) for z in e["per_zoom"]])
     assert int(covered.sum()) == e["tiles"], "extrapolated counts do not match this batch's zoom mix"
     rest = int((~covered).sum())
-    return {"alg_bytes": e["alg_bytes"] + 8192 * rest, "alg_flops": e["alg_flops"],
+    return {"alg_bytes": e["alg_bytes"] + e.get("mask_bytes", 8192) * rest, "alg_flops": e["alg_flops"],
+            "alg_bytes_upper_bound": e.get("alg_bytes_upper_bound", False),
             "extrapolated": f"{keys[0]}: {e['tiles']} requests at zooms {min(map(int, e['per_zoom']))}-"
                             f"{max(map(int, e['per_zoom']))} extrapolated per zoom from the oracle's counts on a "
                             f"sample of them; the {rest} other requests count their mask bytes only (a lower "
@@ -604,7 +606,7 @@ def main():
         # stream they run on
         aa_frontier_ms, aa_query_ms = hv.hv_time_aa(reqs, out_aa, launch, reps=5)
         aa["roofline"] = roofline_record(
-            wl["name"] + "/aa", launch, aa_frontier_ms, aa_query_ms,
+            wl["name"] + "/aa", launch, aa_frontier_ms, aa_query_ms, zooms=tiles[:, 0],
             kernel=f"{query_kernel_name(launch)} (child tiles) + {query_kernel_name(launch, aa=True)} (one pass)")
         del out_aa
         stage(f"anti-aliased: {n / aa_s:.0f} tiles/s")

@@ -16,9 +16,9 @@ brute force of N_box and N_unlit_cand).  Per-zoom sums are kept beside the
 totals.
 
 Calls only the oracle and the seeded generators.  Usage:
-    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4] [c3] [c4fill] [c1aa] [c2aa] [c4aa]
+    python tests/golden/make_algorithmic_work.py [c1] [c2] [c4] [c3] [c4fill] [c1aa] [c2aa] [c4aa] [c3aa]
 (c3: sampled and extrapolated per zoom, see c3_sampled; c4fill: the fill
-counters, see c4fill; c<k>aa: anti-aliased output of c<k>, see aa_counts).
+counters, see c4fill; c<k>aa: anti-aliased output of c<k>, see aa_counts; c3aa sampled as c3).
 """
 from __future__ import annotations
 
@@ -57,13 +57,16 @@ def workload(key):
     raise KeyError(key)
 
 
-def c3_sampled(data):
+def c3_sampled(data, aa=False):
     """The 1e9 points cannot be indexed whole on the host.  Their work is
     counted on the zoom-stratified sample of tests/golden/fullsize_c3.npz (27
     requests per zoom at zooms 3-18, each tile against an oracle index over
     the points near it, as make_fullsize_parity.py does) and extrapolated per
     zoom to every request of the 10,000 at those zooms: the mean per sampled
-    tile of a zoom times the number of requests at that zoom."""
+    tile of a zoom times the number of requests at that zoom.  aa: the
+    anti-aliased output instead, each sampled request counted over its four
+    child tiles at 2r (see aa_counts), whose reach lies inside the parent's
+    near points."""
     import make_fullsize_parity as mfp
     from helpers import stratified_sample
     name = "points-1e9-clustered-10000tiles-z0-18-r1-3"
@@ -94,30 +97,45 @@ def c3_sampled(data):
         sub = np.concatenate([pts[start[cy * 256 + xa]:start[cy * 256 + xb + 1]]
                               for cy in range(max(0, y0 - 1), min(255, y1 + 1) + 1)])
         if len(sub):
-            cnt[k] = oracle.OracleIndex(sub, oracle.POINTS).render(tiles[t:t + 1], r[t:t + 1], want_bit=False,
-                                                                   want_counters=True)["counters"][0]
+            if aa:
+                kids = np.array([[z + 1, 2 * x + a, 2 * y + b] for b in (0, 1) for a in (0, 1)], dtype=np.int64)
+                cnt[k] = oracle.OracleIndex(sub, oracle.POINTS).render(
+                    kids, np.full(4, 2.0 * r[t]), want_bit=False, want_counters=True)["counters"].sum(0)
+            else:
+                cnt[k] = oracle.OracleIndex(sub, oracle.POINTS).render(tiles[t:t + 1], r[t:t + 1], want_bit=False,
+                                                                       want_counters=True)["counters"][0]
         if k % 20 == 0:
             print(f"{name}: sampled tile {k + 1}/{len(idx)} z{z}, {time.time() - t0:.0f}s", flush=True)
     zooms, tot_b, tot_f, tot_n = {}, 0.0, 0.0, 0
+    mask = 65536 if aa else 8192
     for z in np.unique(tiles[idx, 0]):
         sel = tiles[idx, 0] == z
         n_z = int((tiles[:, 0] == z).sum())
         cz = cnt[sel].mean(0)
-        b = 8192 + 16 * cz[oracle.C_UNLIT_CAND]
+        b = mask + 16 * cz[oracle.C_UNLIT_CAND]
         f = 6 * (cz[oracle.C_NBOX_UNLIT] + cz[oracle.C_LIT])
         zooms[str(int(z))] = {"sampled_tiles": int(sel.sum()), "requests": n_z, "bytes_per_tile": float(b),
                               "flops_per_tile": float(f)}
         tot_b += n_z * b
         tot_f += n_z * f
         tot_n += n_z
-    data[name + "/zooms-3-18-extrapolated"] = {
+    key = name + ("/aa" if aa else "") + "/zooms-3-18-extrapolated"
+    data[key] = {
         "tiles": tot_n, "objects": n, "alg_bytes": int(round(tot_b)), "alg_flops": int(round(tot_f)),
-        "bytes_per_tile": tot_b / tot_n, "per_zoom": zooms, "extrapolated": True,
+        "bytes_per_tile": tot_b / tot_n, "per_zoom": zooms, "extrapolated": True, "mask_bytes": mask,
         "note": "counted by the oracle on 27 sampled requests per zoom at zooms 3-18 and extrapolated per zoom to "
                 "the requests of the 10,000 at those zooms (zooms 0-2 are not covered); bytes = 8192 per mask + "
                 "16 per point needed to certify an unlit pixel; flops = 6 per (unlit pixel, box-meeting point) "
                 "pair + one witness test per lit pixel"}
-    print(name, {k: v for k, v in data[name + "/zooms-3-18-extrapolated"].items() if k != "per_zoom"}, flush=True)
+    if aa:
+        data[key]["alg_bytes_upper_bound"] = True
+        data[key]["note"] = ("anti-aliased output, counted by the oracle over the four child tiles at 2r of 27 "
+                             "sampled requests per zoom at zooms 3-18 and extrapolated per zoom to the requests of "
+                             "the 10,000 at those zooms (zooms 0-2 are not covered); bytes = 65536 per tile + 16 per "
+                             "point needed to certify an unlit sub-sample, summed over the children (an upper "
+                             "bound); flops = 6 per (unlit sub-sample, box-meeting point) pair + one witness test "
+                             "per lit sub-sample")
+    print(key, {k: v for k, v in data[key].items() if k != "per_zoom"}, flush=True)
 
 
 def c4fill(data):
@@ -215,11 +233,12 @@ def aa_counts(data, key):
 
 def main(keys):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
-    if "c3" in keys:
-        keys = [k for k in keys if k != "c3"]
-        c3_sampled(data)
-        with open(OUT, "w") as fh:
-            json.dump(data, fh, indent=1, sort_keys=True)
+    for key in ("c3", "c3aa"):
+        if key in keys:
+            keys = [k for k in keys if k != key]
+            c3_sampled(data, aa=key == "c3aa")
+            with open(OUT, "w") as fh:
+                json.dump(data, fh, indent=1, sort_keys=True)
     for key in [k for k in keys if k.endswith("aa")]:
         keys = [k for k in keys if k != key]
         aa_counts(data, key[:-2])
